@@ -1,0 +1,209 @@
+/*
+ * gpe.h -- C ABI of the MI355X ground-state library.
+ *
+ * Computes ground states of a Bose-Einstein condensate, the minimiser of the
+ * discretised Gross-Pitaevskii energy on the unit sphere, with the feasible
+ * gradient method (BB step, Cayley retraction, nonmonotone search; §3.1,
+ * Algorithm 1) and the regularized Newton method (§3.2, Algorithm 2), on one
+ * AMD Instinct MI355X (gfx950).  The problem statement follows §1-§2 of the
+ * paper: a box U, a grid, a trap V, interaction beta and rotation Omega in;
+ * the ground state phi, energy E, chemical potential mu and residual
+ * ||H(phi)phi - mu phi||_inf out.
+ *
+ * Conventions shared by every entry point:
+ *  - Grid (Fourier pseudospectral, §2.3): n[i] unique periodic points per
+ *    axis, x_j = lo[i] + j h_i, h_i = (hi[i]-lo[i]) / n[i], j = 0..n[i]-1.
+ *    n[i] must be a power of two, 16 <= n[i] <= 1024.
+ *  - Layout: x fastest, then y, then z; interleaved (re, im) complex.
+ *  - phi is in physical units: ||phi||_h^2 = h_vol sum |phi_j|^2 (h_vol = prod h_i).
+ *  - "X units" (the unified problem of §3): X = sqrt(h_vol) phi, so that
+ *    ||X||_2 = ||phi||_h, F(X) = E_h(phi), A = 2 H_lin, alpha = beta/(2 h_vol).
+ *  - Every pointer to field data is DEVICE memory owned by the caller; the
+ *    library keeps no pointer after a call returns.  Host pointers (problem,
+ *    options, result, scalars) are read or written during the call only.
+ *  - All device work is ordered on the context's stream (gpe_ctx_create).
+ *  - Errors are status codes; no C++ exception crosses this interface.  A
+ *    context must not be used from two threads at once.
+ */
+#ifndef GPE_H
+#define GPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GPE_OK               0
+#define GPE_NOT_CONVERGED    1   /* iteration cap hit; outputs hold the last iterate */
+#define GPE_EINVAL          -1   /* null pointer, bad dim/box/sizes, Omega != 0 where not allowed, zero phi0 */
+#define GPE_EUNSUPPORTED    -2   /* n not a power of two in [16, 1024], or an unsupported combination */
+#define GPE_ENOMEM          -3   /* device allocation failed */
+#define GPE_EDEVICE         -4   /* HIP runtime error (see gpe_last_error) */
+#define GPE_ENONFINITE      -5   /* a reduction became NaN/Inf (bad V, phi0 or divergence) */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define GPE_BC_FOURIER       0   /* periodic, Fourier pseudospectral (§2.3) */
+
+#define GPE_PREC_FP64        0   /* every array and FFT in float64 */
+#define GPE_PREC_MIXED       1   /* FP32 FFT/pointwise bulk, FP64 reductions, scalars and outer Newton state */
+
+#define GPE_ALG1             1   /* Algorithm 1 alone (§3.1) */
+#define GPE_ALG2             2   /* Algorithm 2: K_init steps of Algorithm 1, then regularized Newton (§3.2) */
+
+/* ---- problem ------------------------------------------------------------ */
+typedef struct gpe_problem {
+    int32_t dim;          /* 1, 2 or 3 */
+    int32_t bc;           /* GPE_BC_FOURIER */
+    int32_t n[3];         /* points per axis (x, y, z); entries beyond dim ignored */
+    double lo[3], hi[3];  /* box U = prod (lo_i, hi_i), lo_i < hi_i */
+    double beta;          /* interaction constant */
+    double omega;         /* rotation speed; must be 0 when dim == 1 */
+    double gamma[3];      /* harmonic trap V = 1/2 sum gamma_i^2 x_i^2 (§1) */
+    double lattice_amp;   /* optical lattice A * sum sin^2(k x_i) (§4.2, §4.4); 0 = none */
+    double lattice_k;     /* k of the lattice (pi/4 in the paper) */
+    const double* v;      /* optional DEVICE array of V (float64, grid layout); NULL = analytic V */
+} gpe_problem;
+
+/* ---- options (defaults from gpe_options_default) ------------------------ */
+typedef struct gpe_options {
+    int32_t precision;    /* GPE_PREC_FP64 or GPE_PREC_MIXED */
+    int32_t algorithm;    /* GPE_ALG1 or GPE_ALG2 */
+    double tol;           /* stop when ||H(phi)phi - mu phi||_inf < tol (phi units) */
+    int32_t k_init;       /* Algorithm 1 steps before the Newton loop (100, §4.3) */
+    int32_t k_sub;        /* max Algorithm 1 steps per Newton subproblem (200, §4.3) */
+    int32_t max_outer;    /* max Newton steps */
+    int32_t max_iter;     /* max steps of Algorithm 1 when run alone */
+    int32_t m_max;        /* max backtracks per step (the last trial is taken) */
+    double tau0;          /* first BB step */
+    double rho1, eta, sigma;              /* nonmonotone Armijo: rho_1, eta, backtracking factor */
+    double renorm_tol;                    /* renormalise when | ||X||^2 - 1 | > renorm_tol (§4) */
+    double eta1, eta2, gamma_shrink, gamma_grow;  /* trust-region ratio test and delta update (§3.2) */
+    double delta0, delta_min, delta_max;          /* regularisation delta */
+    int32_t chunk;        /* evaluations per host check of the done flags (graph size) */
+    int32_t use_graph;    /* 1: replay chunks as a captured hipGraph; 0: plain launches */
+    int32_t profile;      /* 1: time every launch of the last-axis pass with HIP events */
+    int32_t reserved0;
+} gpe_options;
+
+/* ---- results ------------------------------------------------------------ */
+typedef struct gpe_result {
+    int32_t status;       /* GPE_OK / GPE_NOT_CONVERGED / negative error */
+    int32_t outer_iters;  /* Newton steps taken */
+    int32_t inner_iters;  /* Algorithm 1 steps taken (all runs) */
+    int32_t nfe;          /* function+gradient evaluations (all precisions) */
+    int32_t nfe_fp64;     /* of which evaluated in float64 */
+    int32_t backtracks;   /* step-size reductions */
+    int32_t rejections;   /* rejected Newton trial points */
+    int32_t reserved;
+    double energy;        /* E_h(phi)  (§2) */
+    double mu;            /* E + beta/2 int |phi|^4  (§1) */
+    double resid;         /* ||H(phi)phi - mu phi||_inf */
+    double norm_err;      /* ||phi||_h^2 - 1 */
+    double rms[3];        /* sqrt(int x_i^2 |phi|^2)  (§4, rms) */
+    double max_dens;      /* max |phi|^2 */
+    double delta;         /* final regularisation delta */
+    double time_ms;       /* device time of the solve (events on the context stream) */
+    int32_t nfe_f;        /* evaluations of F in Algorithm 1 (including the initial one) */
+    int32_t nfe_w;        /* evaluations of the Newton model W */
+    int32_t nfe_outer;    /* float64 evaluations of F at outer iterates */
+    int32_t pass_launches;/* profile: timed launches of the last-axis pass (solver active) */
+    double pass_ms;       /* profile: summed event time of those launches */
+} gpe_result;
+
+typedef struct gpe_ctx gpe_ctx;
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t the
+ * caller owns (NULL = the legacy default stream); the library orders its own
+ * work after the caller's work on it and makes the caller's stream wait for
+ * the library's work before returning.  Returns GPE_OK or an error. */
+int gpe_ctx_create(gpe_ctx** out, int device, void* stream);
+/* Free every device buffer the context owns.  Safe on NULL. */
+int gpe_ctx_destroy(gpe_ctx* ctx);
+
+void gpe_options_default(gpe_options* opts);
+const char* gpe_strerror(int status);
+/* Text of the last HIP error seen by the calling thread ("" if none). */
+const char* gpe_last_error(void);
+
+/*
+ * H(phi) phi = (-1/2 Laplacian + V - Omega L_z + beta |phi|^2) phi on the
+ * Fourier grid (§1; operator of §2.3 with the per-axis multipliers
+ * lambda^2/2 + Omega y lambda on x-lines and eta^2/2 - Omega x eta on y-lines).
+ *   precision  GPE_PREC_FP64: phi, h_phi are complex128;
+ *              GPE_PREC_MIXED: complex64 arrays, FP32 FFTs, FP64 reductions.
+ *   phi        DEVICE input (not modified); h_phi DEVICE output (may not alias phi).
+ *   scalars    HOST double[10] out or NULL: E_h(phi), mu = E + beta/2 int|phi|^4,
+ *              ||H(phi)phi - mu phi||_inf, ||phi||_h^2, rms x, y, z, max|phi|^2,
+ *              kinetic+rotation part of E, potential part of E.
+ * Blocks until the scalars are on the host when scalars != NULL.
+ */
+int gpe_apply_h(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision,
+                const void* phi, void* h_phi, double* scalars);
+
+/*
+ * Hessian-vector product of the regularized Newton model (Lemma 3.1, §3.2),
+ * in X units:  out = A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s.
+ * x_k, s, out: DEVICE complex128 arrays (out may not alias the inputs).
+ */
+int gpe_hess_vec(gpe_ctx* ctx, const gpe_problem* prob, const void* x_k, const void* s,
+                 double delta, void* out);
+
+/*
+ * Cayley retraction (§3.1, Theorem 3.3) in the real reading: with
+ * a = Re(x^* g), n_x = ||x||^2, n_g = ||g||^2,
+ *   y = p x + q g,  p = ((1 + tau a)^2 - tau^2 n_x n_g)/den,  q = -2 tau n_x/den,
+ *   den = 1 - tau^2 a^2 + tau^2 n_x n_g.
+ * x, g, y: DEVICE complex128 arrays of m elements (y may alias neither).
+ * coeffs: HOST double[5] out or NULL: p, q, a, n_x, n_g.  Blocks.
+ */
+int gpe_retract(gpe_ctx* ctx, int64_t m, const void* x, const void* g, double tau,
+                void* y, double* coeffs);
+
+/*
+ * Ground state by Algorithm 1 or 2 (§3).  phi: DEVICE complex128 array; on
+ * entry the initial guess phi_0 (need not be normalised, must be nonzero),
+ * on exit the computed state with ||phi||_h = 1.  The result's energy, mu,
+ * resid, rms and max_dens are recomputed in float64 from the returned phi.
+ * Returns result->status.
+ */
+int gpe_solve(gpe_ctx* ctx, const gpe_problem* prob, const gpe_options* opts,
+              void* phi, gpe_result* result);
+
+/*
+ * `count` independent problems solved together: every evaluation step runs
+ * all unfinished problems in the same kernel launches.  Problems may differ
+ * in beta, Omega, V and n (same dim).  phis[i]: DEVICE complex128 arrays.
+ * results: HOST array of `count`.  Returns GPE_OK if every problem
+ * converged, GPE_NOT_CONVERGED if any did not, or the first error.
+ */
+int gpe_solve_batched(gpe_ctx* ctx, int32_t count, const gpe_problem* probs,
+                      const gpe_options* opts, void* const* phis, gpe_result* results);
+
+/*
+ * Trigonometric prolongation for the cascadic multigrid (Algorithm 3): the
+ * coarse grid function (n points per axis) is interpolated to 2n points per
+ * axis on the same box (coarse points are every other fine point); per axis
+ * the spectrum is zero-padded and the coarse Nyquist coefficient split half
+ * and half between +n and -n.  phi_c, phi_f: DEVICE complex128 arrays.
+ * fine must equal coarse with every n doubled.
+ */
+int gpe_prolong(gpe_ctx* ctx, const gpe_problem* coarse, const gpe_problem* fine,
+                const void* phi_c, void* phi_f);
+
+/*
+ * Algorithm 3: cascadic multigrid over `nlevels` grids (n doubling per
+ * level, coarse problem given), each level solved by gpe_solve_batched for
+ * all `count` problems, coarse levels to `level_tol`, the finest to opts->tol.
+ * phi0s[i]: DEVICE complex128 initial data on the coarse grid (read only);
+ * phis[i]: DEVICE complex128 outputs on the finest grid.
+ */
+int gpe_solve_cascadic(gpe_ctx* ctx, int32_t count, const gpe_problem* coarse,
+                       int32_t nlevels, double level_tol, const gpe_options* opts,
+                       void* const* phi0s, void* const* phis, gpe_result* results);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPE_H */

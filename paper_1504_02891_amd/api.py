@@ -1,0 +1,190 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Device memory and streams come from PyTorch: field arrays are CUDA/HIP
+tensors, and every call runs on ``torch.cuda.current_stream()`` order.
+All arithmetic happens in libgpe.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import torch
+
+from . import _native as N
+
+
+class GpeError(RuntimeError):
+    def __init__(self, status, where):
+        L = N.lib()
+        msg = L.gpe_strerror(status).decode()
+        extra = L.gpe_last_error().decode()
+        super().__init__(f"{where}: status {status} ({msg}) {extra}".strip())
+        self.status = status
+
+
+def _check(status, where, allow=(N.GPE_OK,)):
+    if status not in allow:
+        raise GpeError(status, where)
+    return status
+
+
+_CTX = {}
+
+
+def context(device=None):
+    """Library context bound to ``device`` and the current torch stream."""
+    if device is None:
+        device = torch.cuda.current_device()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    key = (int(device), int(stream))
+    ctx = _CTX.get(key)
+    if ctx is None:
+        h = C.c_void_p()
+        _check(N.lib().gpe_ctx_create(C.byref(h), int(device), C.c_void_p(stream)), "gpe_ctx_create")
+        ctx = h
+        _CTX[key] = ctx
+    return ctx
+
+
+def problem_struct(p, v=None):
+    """gpe_problem from an object with the fields of workloads.Problem.
+    ``v``: optional CUDA float64 tensor with the potential on the grid."""
+    s = N.Problem()
+    s.dim = int(p.dim)
+    s.bc = N.GPE_BC_FOURIER
+    for i in range(3):
+        s.n[i] = int(p.n[i]) if i < p.dim else 1
+        s.lo[i] = float(p.lo[i]) if i < p.dim else 0.0
+        s.hi[i] = float(p.hi[i]) if i < p.dim else 1.0
+        s.gamma[i] = float(p.gamma[i])
+    s.beta = float(p.beta)
+    s.omega = float(p.omega)
+    s.lattice_amp = float(getattr(p, "lattice_amp", 0.0))
+    s.lattice_k = float(getattr(p, "lattice_k", math.pi / 4))
+    s.v = C.c_void_p(v.data_ptr()) if v is not None else None
+    if getattr(p, "bc", "fourier") != "fourier":
+        s.bc = 1  # rejected by the library (sine transform not exported)
+    return s
+
+
+def options(**kw):
+    o = N.Options()
+    N.lib().gpe_options_default(C.byref(o))
+    prec = kw.pop("precision", None)
+    if prec is not None:
+        o.precision = {"fp64": N.GPE_PREC_FP64, "mixed": N.GPE_PREC_MIXED}.get(prec, prec)
+    alg = kw.pop("algorithm", None)
+    if alg is not None:
+        o.algorithm = {"alg1": N.GPE_ALG1, "alg2": N.GPE_ALG2}.get(alg, alg)
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _dev_tensor(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+SCALAR_NAMES = ("energy", "mu", "resid", "norm2", "rms_x", "rms_y", "rms_z", "max_dens",
+                "e_kin", "e_pot")
+
+
+def apply_h(p, phi, precision="fp64", v=None):
+    """H(phi) phi on the Fourier grid; returns (h_phi, scalars dict)."""
+    prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
+    dt = torch.complex128 if prec == N.GPE_PREC_FP64 else torch.complex64
+    _dev_tensor(phi, dt, "phi")
+    out = torch.empty_like(phi)
+    sc = (C.c_double * 10)()
+    ps = problem_struct(p, v)
+    _check(N.lib().gpe_apply_h(context(phi.device.index), C.byref(ps), prec, C.c_void_p(phi.data_ptr()),
+                               C.c_void_p(out.data_ptr()), sc), "gpe_apply_h")
+    return out, dict(zip(SCALAR_NAMES, list(sc)))
+
+
+def hess_vec(p, x_k, s, delta, v=None):
+    """A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s (X units)."""
+    _dev_tensor(x_k, torch.complex128, "x_k")
+    _dev_tensor(s, torch.complex128, "s")
+    out = torch.empty_like(s)
+    ps = problem_struct(p, v)
+    _check(N.lib().gpe_hess_vec(context(s.device.index), C.byref(ps), C.c_void_p(x_k.data_ptr()),
+                                C.c_void_p(s.data_ptr()), float(delta), C.c_void_p(out.data_ptr())),
+           "gpe_hess_vec")
+    return out
+
+
+def retract(x, g, tau):
+    """Cayley curve point y = p x + q g; returns (y, dict(p, q, a, nx, ng))."""
+    _dev_tensor(x, torch.complex128, "x")
+    _dev_tensor(g, torch.complex128, "g")
+    y = torch.empty_like(x)
+    co = (C.c_double * 5)()
+    _check(N.lib().gpe_retract(context(x.device.index), x.numel(), C.c_void_p(x.data_ptr()),
+                               C.c_void_p(g.data_ptr()), float(tau), C.c_void_p(y.data_ptr()), co),
+           "gpe_retract")
+    return y, dict(zip(("p", "q", "a", "nx", "ng"), list(co)))
+
+
+def solve(p, phi0, v=None, **opts):
+    """Ground state from phi0 (complex128 CUDA tensor); returns (phi, result dict)."""
+    _dev_tensor(phi0, torch.complex128, "phi0")
+    phi = phi0.clone()
+    res = N.Result()
+    ps = problem_struct(p, v)
+    o = options(**opts)
+    st = N.lib().gpe_solve(context(phi.device.index), C.byref(ps), C.byref(o), C.c_void_p(phi.data_ptr()),
+                           C.byref(res))
+    _check(st, "gpe_solve", allow=(N.GPE_OK, N.GPE_NOT_CONVERGED))
+    return phi, res.as_dict()
+
+
+def solve_batched(probs, phi0s, **opts):
+    n = len(probs)
+    phis = []
+    for i, t in enumerate(phi0s):
+        _dev_tensor(t, torch.complex128, f"phi0s[{i}]")
+        phis.append(t.clone())
+    pa = (N.Problem * n)(*[problem_struct(p) for p in probs])
+    ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in phis])
+    res = (N.Result * n)()
+    o = options(**opts)
+    st = N.lib().gpe_solve_batched(context(phis[0].device.index), n, pa, C.byref(o), ptrs, res)
+    _check(st, "gpe_solve_batched", allow=(N.GPE_OK, N.GPE_NOT_CONVERGED))
+    return phis, [r.as_dict() for r in res]
+
+
+def prolong(p_coarse, p_fine, phi_c):
+    _dev_tensor(phi_c, torch.complex128, "phi_c")
+    shape = tuple(int(n) for n in reversed(p_fine.n[: p_fine.dim]))
+    out = torch.empty(shape, dtype=torch.complex128, device=phi_c.device)
+    a, b = problem_struct(p_coarse), problem_struct(p_fine)
+    _check(N.lib().gpe_prolong(context(phi_c.device.index), C.byref(a), C.byref(b),
+                               C.c_void_p(phi_c.data_ptr()), C.c_void_p(out.data_ptr())), "gpe_prolong")
+    return out
+
+
+def solve_cascadic(p_coarse_list, phi0s, nlevels, level_tol=1e-4, **opts):
+    n = len(p_coarse_list)
+    for i, t in enumerate(phi0s):
+        _dev_tensor(t, torch.complex128, f"phi0s[{i}]")
+    fine = []
+    for p in p_coarse_list:
+        shape = tuple(int(k) << (nlevels - 1) for k in reversed(p.n[: p.dim]))
+        fine.append(torch.empty(shape, dtype=torch.complex128, device=phi0s[0].device))
+    pa = (N.Problem * n)(*[problem_struct(p) for p in p_coarse_list])
+    ins = (C.c_void_p * n)(*[t.data_ptr() for t in phi0s])
+    outs = (C.c_void_p * n)(*[t.data_ptr() for t in fine])
+    res = (N.Result * n)()
+    o = options(**opts)
+    st = N.lib().gpe_solve_cascadic(context(phi0s[0].device.index), n, pa, int(nlevels), float(level_tol),
+                                    C.byref(o), ins, outs, res)
+    _check(st, "gpe_solve_cascadic", allow=(N.GPE_OK, N.GPE_NOT_CONVERGED))
+    return fine, [r.as_dict() for r in res]

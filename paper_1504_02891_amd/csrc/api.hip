@@ -1,0 +1,787 @@
+// C ABI of the ground-state library: context, workspace, validation, launch
+// geometry and the host loop that replays chunks of solver evaluations.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gpe.h"
+#include "gpe_launch.h"
+
+using namespace gpe;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e_);           \
+      return GPE_EDEVICE;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define CHK(expr)                 \
+  do {                            \
+    int r_ = (expr);              \
+    if (r_ < 0) return r_;        \
+  } while (0)
+
+constexpr int kSolverThreads = 128;   // threads per workgroup of every solver pass
+constexpr int kApplyThreads = 128;
+
+// Workspace slots owned by a context (grown on demand, freed at destroy).
+enum WsSlot {
+  WS_PROB = 0, WS_STATE, WS_BMAP0, WS_BMAP1, WS_BMAP2, WS_VAXIS, WS_ARENA,
+  WS_APPLY_T, WS_APPLY_PART, WS_APPLY_OUT, WS_APPLY_RPART, WS_APPLY_PROB, WS_APPLY_VAXIS,
+  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_COUNT
+};
+
+}  // namespace
+
+struct gpe_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+  void* twd = nullptr;
+  void* twf = nullptr;
+  void* ws[WS_COUNT] = {};
+  size_t ws_size[WS_COUNT] = {};
+  void* pinned = nullptr;       // host staging for uploads / small downloads
+  size_t pinned_size = 0;
+};
+
+namespace {
+
+int ws_get(gpe_ctx* c, int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  if (c->ws_size[slot] < bytes) {
+    if (c->ws[slot]) {
+      HIPCHK(hipStreamSynchronize(c->s));
+      HIPCHK(hipFree(c->ws[slot]));
+      c->ws[slot] = nullptr;
+      c->ws_size[slot] = 0;
+    }
+    size_t b = bytes + bytes / 8;
+    if (hipMalloc(&c->ws[slot], b) != hipSuccess) {
+      (void)hipGetLastError();
+      g_last_error = "hipMalloc failed for " + std::to_string(b) + " bytes";
+      return GPE_ENOMEM;
+    }
+    c->ws_size[slot] = b;
+  }
+  *out = c->ws[slot];
+  return GPE_OK;
+}
+
+int pinned_get(gpe_ctx* c, size_t bytes, void** out) {
+  if (c->pinned_size < bytes) {
+    if (c->pinned) {
+      HIPCHK(hipStreamSynchronize(c->s));
+      HIPCHK(hipHostFree(c->pinned));
+      c->pinned = nullptr;
+    }
+    HIPCHK(hipHostMalloc(&c->pinned, bytes + 4096, hipHostMallocDefault));
+    c->pinned_size = bytes + 4096;
+  }
+  *out = c->pinned;
+  return GPE_OK;
+}
+
+// Stream-ordered upload through the pinned staging buffer.  The caller has
+// synchronised the context stream, so the staging memory is free.
+int upload(gpe_ctx* c, void* dst, const void* src, size_t bytes, size_t staging_off) {
+  void* pin;
+  CHK(pinned_get(c, staging_off + bytes, &pin));
+  std::memcpy((char*)pin + staging_off, src, bytes);
+  HIPCHK(hipMemcpyAsync(dst, (char*)pin + staging_off, bytes, hipMemcpyHostToDevice, c->s));
+  return GPE_OK;
+}
+
+int begin_call(gpe_ctx* c) {
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipEventRecord(c->ev_in, c->user));
+  HIPCHK(hipStreamWaitEvent(c->s, c->ev_in, 0));
+  return GPE_OK;
+}
+int end_call(gpe_ctx* c) {
+  HIPCHK(hipEventRecord(c->ev_out, c->s));
+  HIPCHK(hipStreamWaitEvent(c->user, c->ev_out, 0));
+  return GPE_OK;
+}
+
+bool pow2_ok(int n) { return n >= 16 && n <= kMaxN && (n & (n - 1)) == 0; }
+
+// Validate a problem and fill the device descriptor's geometry and scalars
+// (array pointers are set by the caller); `vaxis` receives the separable
+// potential tables V_i(x_i) = 1/2 gamma_i^2 x_i^2 + A sin^2(k x_i).
+int build_prob(const gpe_problem* p, ProbDev* d, double* vaxis) {
+  if (!p || !d) return GPE_EINVAL;
+  if (p->dim < 1 || p->dim > 3) return GPE_EINVAL;
+  if (p->bc != GPE_BC_FOURIER) return GPE_EUNSUPPORTED;
+  if (!std::isfinite(p->beta) || !std::isfinite(p->omega)) return GPE_EINVAL;
+  if (p->dim == 1 && p->omega != 0.0) return GPE_EINVAL;
+  std::memset(d, 0, sizeof(*d));
+  d->dim = p->dim;
+  d->m = 1;
+  double hvol = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    if (i < p->dim) {
+      if (!pow2_ok(p->n[i])) return GPE_EUNSUPPORTED;
+      if (!(p->lo[i] < p->hi[i]) || !std::isfinite(p->lo[i]) || !std::isfinite(p->hi[i])) return GPE_EINVAL;
+      d->n[i] = p->n[i];
+      d->lo[i] = p->lo[i];
+      d->len[i] = p->hi[i] - p->lo[i];
+      d->h[i] = d->len[i] / p->n[i];
+      hvol *= d->h[i];
+    } else {
+      d->n[i] = 1;
+      d->lo[i] = 0.0;
+      d->len[i] = 1.0;
+      d->h[i] = 1.0;
+    }
+  }
+  d->stride[0] = 1;
+  d->stride[1] = d->n[0];
+  d->stride[2] = (int64_t)d->n[0] * d->n[1];
+  d->m = (int64_t)d->n[0] * d->n[1] * d->n[2];
+  d->beta = p->beta;
+  d->omega = p->omega;
+  d->hvol = hvol;
+  d->sqrt_hvol = std::sqrt(hvol);
+  d->alpha = p->beta / (2.0 * hvol);
+  d->has_v = p->v != nullptr;
+  d->v_arr = p->v;
+  if (vaxis) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < kMaxN; ++j) {
+        double v = 0.0;
+        if (i < p->dim && j < p->n[i]) {
+          const double x = d->lo[i] + d->h[i] * j;
+          const double s = std::sin(p->lattice_k * x);
+          v = 0.5 * p->gamma[i] * p->gamma[i] * x * x + p->lattice_amp * s * s;
+        }
+        vaxis[i * kMaxN + j] = v;
+      }
+  }
+  return GPE_OK;
+}
+
+struct Geom {
+  int threads, lanes, tiles;
+  size_t smem;
+};
+
+// Tiling of a pass along axis `ax`: lines of N = n[ax] points, TL = N/16
+// threads per line, `threads / TL` lines per workgroup.
+Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem) {
+  Geom g;
+  const int N = d.n[ax];
+  const int TL = N / 16;
+  g.threads = threads < TL ? TL : threads;
+  g.lanes = g.threads / TL;
+  const int64_t cols = d.m / N;
+  g.tiles = (int)((cols + g.lanes - 1) / g.lanes);
+  g.smem = strided ? (size_t)N * (g.lanes + 1) * elem : (size_t)g.lanes * (N + N / 16) * elem;
+  return g;
+}
+
+void set_default(gpe_options* o) {
+  o->precision = GPE_PREC_FP64;
+  o->algorithm = GPE_ALG2;
+  o->tol = 1e-6;
+  o->k_init = 100;
+  o->k_sub = 200;
+  o->max_outer = 2000;
+  o->max_iter = 20000;
+  o->m_max = 20;
+  o->tau0 = 1e-3;
+  o->rho1 = 1e-4;
+  o->eta = 0.85;
+  o->sigma = 0.5;
+  o->renorm_tol = 1e-14;
+  o->eta1 = 0.01;
+  o->eta2 = 0.9;
+  o->gamma_shrink = 0.5;
+  o->gamma_grow = 4.0;
+  o->delta0 = 1.0;
+  o->delta_min = 1e-12;
+  o->delta_max = 1e12;
+  o->chunk = 64;
+  o->use_graph = 1;
+  o->profile = 0;
+  o->reserved0 = 0;
+}
+
+// ---------------------------------------------------------------------------
+// apply_h / hess_vec
+// ---------------------------------------------------------------------------
+int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a, double* scalars) {
+  ProbDev d;
+  std::vector<double> vaxis(3 * kMaxN);
+  CHK(build_prob(prob, &d, vaxis.data()));
+  const size_t elem = fp64 ? 16 : 8;
+  Geom g[3];
+  int maxt = 1;
+  for (int ax = 0; ax < d.dim; ++ax) {
+    g[ax] = pass_geom(d, ax, ax > 0, kApplyThreads, elem);
+    if (d.dim == 1) g[ax] = pass_geom(d, 0, false, 64, elem);
+    d.tiles[ax] = g[ax].tiles;
+    d.lanes[ax] = g[ax].lanes;
+    maxt = std::max(maxt, g[ax].tiles);
+  }
+  void *t, *part, *vax, *pd, *rpart, *out;
+  CHK(ws_get(c, WS_APPLY_T, (size_t)d.m * elem, &t));
+  CHK(ws_get(c, WS_APPLY_PART, (size_t)maxt * SA_COUNT * sizeof(double), &part));
+  CHK(ws_get(c, WS_APPLY_VAXIS, vaxis.size() * sizeof(double), &vax));
+  CHK(ws_get(c, WS_APPLY_PROB, sizeof(ProbDev), &pd));
+  const int nr = (int)std::min<int64_t>((d.m + 255) / 256, 1024);
+  CHK(ws_get(c, WS_APPLY_RPART, nr * sizeof(double), &rpart));
+  CHK(ws_get(c, WS_APPLY_OUT, 16 * sizeof(double), &out));
+  d.t = t;
+  d.partF = (double*)part;
+  d.part1 = (double*)part;
+  d.v_axis = (const double*)vax;
+  CHK(upload(c, vax, vaxis.data(), vaxis.size() * sizeof(double), 0));
+  CHK(upload(c, pd, &d, sizeof(d), vaxis.size() * sizeof(double)));
+  const void* tw = fp64 ? c->twd : c->twf;
+  const ProbDev* P = (const ProbDev*)pd;
+  if (d.dim == 1) {
+    launch_apply_pass(c->s, R_SOLO, fp64, g[0].tiles, g[0].threads, g[0].smem, P, a, tw);
+  } else {
+    launch_apply_pass(c->s, R_FIRST, fp64, g[0].tiles, g[0].threads, g[0].smem, P, a, tw);
+    if (d.dim == 3) launch_apply_pass(c->s, R_MID, fp64, g[1].tiles, g[1].threads, g[1].smem, P, a, tw);
+    launch_apply_pass(c->s, R_FINAL, fp64, g[d.dim - 1].tiles, g[d.dim - 1].threads, g[d.dim - 1].smem, P, a, tw);
+  }
+  HIPCHK(hipGetLastError());
+  if (a.kind == 0) {
+    launch_apply_resid(c->s, nr, P, a.in, a.out, (double*)rpart, fp64);
+    launch_apply_finalize(c->s, P, (const double*)rpart, nr, (double*)out);
+    HIPCHK(hipGetLastError());
+    if (scalars) {
+      void* pin;
+      CHK(pinned_get(c, 16 * sizeof(double), &pin));
+      HIPCHK(hipMemcpyAsync(pin, out, 10 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+      std::memcpy(scalars, pin, 10 * sizeof(double));
+    }
+  }
+  return GPE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solver
+// ---------------------------------------------------------------------------
+struct ProbLayout {
+  size_t off_xf[2], off_gf[2], off_s[2], off_d[2], off_xk, off_gk, off_t, off_p1, off_pf;
+};
+
+void init_state(SolverState& S, const gpe_options& o) {
+  std::memset(&S, 0, sizeof(S));
+  S.mode = M_F;
+  S.phase = PH_INIT;
+  S.cur = 0;
+  S.force_norm = 1;
+  S.alg = o.algorithm;
+  S.p = 1.0; S.q = 0.0; S.pm1 = 0.0;
+  S.a_b = 0.0; S.n_b = 1.0; S.ng_b = 0.0;
+  S.delta = o.delta0;
+  S.tol = o.tol; S.tau0 = o.tau0; S.rho1 = o.rho1; S.eta = o.eta; S.sigma = o.sigma;
+  S.renorm_tol = o.renorm_tol;
+  S.eta1 = o.eta1; S.eta2 = o.eta2; S.gshrink = o.gamma_shrink; S.ggrow = o.gamma_grow;
+  S.delta_min = o.delta_min; S.delta_max = o.delta_max;
+  S.k_init = o.k_init; S.k_sub = o.k_sub; S.m_max = o.m_max; S.max_iter = o.max_iter;
+  S.max_outer = o.max_outer;
+}
+
+int check_options(const gpe_options* o) {
+  if (!o) return GPE_EINVAL;
+  if (o->precision != GPE_PREC_FP64 && o->precision != GPE_PREC_MIXED) return GPE_EINVAL;
+  if (o->algorithm != GPE_ALG1 && o->algorithm != GPE_ALG2) return GPE_EINVAL;
+  if (!(o->tol >= 0.0) || o->k_sub < 1 || o->k_init < 0 || o->max_outer < 0 || o->max_iter < 0 || o->m_max < 0)
+    return GPE_EINVAL;
+  if (!(o->sigma > 0.0 && o->sigma < 1.0) || !(o->eta >= 0.0 && o->eta < 1.0) || !(o->tau0 > 0.0))
+    return GPE_EINVAL;
+  if (o->chunk < 1 || o->chunk > 4096) return GPE_EINVAL;
+  return GPE_OK;
+}
+
+// Upper bound on the evaluations the device state machine can take before
+// its own caps end every problem (a host-side guard only).
+int64_t eval_cap(const gpe_options& o) {
+  const int64_t per = o.m_max + 2;
+  if (o.algorithm == GPE_ALG1) return (int64_t)(o.max_iter + 2) * per + 16;
+  return (int64_t)(o.k_init + 2) * per + (int64_t)(o.max_outer + 2) * ((int64_t)o.k_sub * per + 4) + 16;
+}
+
+int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
+               gpe_result* results) {
+  if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
+  CHK(check_options(opts));
+  const gpe_options& o = *opts;
+  const int prec64 = o.precision == GPE_PREC_FP64;
+  const size_t es = prec64 ? 16 : 8;       // element size of F / W arrays
+  std::vector<ProbDev> pd(count);
+  std::vector<double> vaxis((size_t)count * 3 * kMaxN);
+  const int dim = probs[0].dim;
+  for (int i = 0; i < count; ++i) {
+    if (!phis[i]) return GPE_EINVAL;
+    CHK(build_prob(&probs[i], &pd[i], &vaxis[(size_t)i * 3 * kMaxN]));
+    if (pd[i].dim != dim) return GPE_EINVAL;
+  }
+  // geometry of each pass for each problem
+  std::vector<Geom> geo((size_t)count * 3);
+  size_t smem[3] = {0, 0, 0};
+  for (int i = 0; i < count; ++i)
+    for (int ax = 0; ax < dim; ++ax) {
+      Geom g = dim == 1 ? pass_geom(pd[i], 0, false, 64, 16) : pass_geom(pd[i], ax, ax > 0, kSolverThreads, 16);
+      geo[(size_t)i * 3 + ax] = g;
+      pd[i].tiles[ax] = g.tiles;
+      pd[i].lanes[ax] = g.lanes;
+      smem[ax] = std::max(smem[ax], g.smem);
+    }
+  const int threads = dim == 1 ? geo[0].threads : kSolverThreads;
+  for (int i = 0; i < count; ++i)
+    if (dim == 1 && geo[(size_t)i * 3].threads != threads) return GPE_EUNSUPPORTED;  // 1D batch: one n
+  // arena layout
+  std::vector<ProbLayout> lay(count);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  for (int i = 0; i < count; ++i) {
+    const size_t m = (size_t)pd[i].m;
+    ProbLayout& L = lay[i];
+    for (int k = 0; k < 2; ++k) {
+      L.off_xf[k] = take(m * es);
+      L.off_gf[k] = take(m * es);
+      L.off_s[k] = take(m * es);
+      L.off_d[k] = take(m * es);
+    }
+    L.off_xk = take(m * 16);
+    L.off_gk = take(m * 16);
+    L.off_t = take(m * 16);
+    L.off_p1 = take((size_t)pd[i].tiles[0] * S1_COUNT * sizeof(double));
+    L.off_pf = take((size_t)std::max(pd[i].tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
+  }
+  CHK(begin_call(c));
+  void *arena, *dprob, *dstate, *dvax, *dbm[3] = {nullptr, nullptr, nullptr};
+  CHK(ws_get(c, WS_ARENA, off, &arena));
+  CHK(ws_get(c, WS_PROB, sizeof(ProbDev) * count, &dprob));
+  CHK(ws_get(c, WS_STATE, sizeof(SolverState) * count, &dstate));
+  CHK(ws_get(c, WS_VAXIS, vaxis.size() * sizeof(double), &dvax));
+  char* A = (char*)arena;
+  for (int i = 0; i < count; ++i) {
+    ProbLayout& L = lay[i];
+    ProbDev& d = pd[i];
+    for (int k = 0; k < 2; ++k) {
+      d.xf[k] = A + L.off_xf[k];
+      d.gf[k] = A + L.off_gf[k];
+      d.s[k] = A + L.off_s[k];
+      d.d[k] = A + L.off_d[k];
+    }
+    d.xk = A + L.off_xk;
+    d.gk = A + L.off_gk;
+    d.t = A + L.off_t;
+    d.part1 = (double*)(A + L.off_p1);
+    d.partF = (double*)(A + L.off_pf);
+    d.v_axis = (const double*)dvax + (size_t)i * 3 * kMaxN;
+  }
+  // block maps: (problem, tile) for each pass
+  std::vector<int2> bm[3];
+  for (int ax = 0; ax < dim; ++ax)
+    for (int i = 0; i < count; ++i)
+      for (int t = 0; t < pd[i].tiles[ax]; ++t) bm[ax].push_back(make_int2(i, t));
+  for (int ax = 0; ax < dim; ++ax) CHK(ws_get(c, WS_BMAP0 + ax, bm[ax].size() * sizeof(int2), &dbm[ax]));
+  std::vector<SolverState> st(count);
+  for (int i = 0; i < count; ++i) init_state(st[i], o);
+  // uploads (staging offsets keep the pieces apart)
+  size_t so = 0;
+  CHK(upload(c, dvax, vaxis.data(), vaxis.size() * sizeof(double), so));
+  so += vaxis.size() * sizeof(double);
+  CHK(upload(c, dprob, pd.data(), sizeof(ProbDev) * count, so));
+  so += sizeof(ProbDev) * count;
+  CHK(upload(c, dstate, st.data(), sizeof(SolverState) * count, so));
+  so += sizeof(SolverState) * count;
+  for (int ax = 0; ax < dim; ++ax) {
+    CHK(upload(c, dbm[ax], bm[ax].data(), bm[ax].size() * sizeof(int2), so));
+    so += bm[ax].size() * sizeof(int2);
+  }
+  const ProbDev* P = (const ProbDev*)dprob;
+  SolverState* S = (SolverState*)dstate;
+  HIPCHK(hipEventRecord(c->t0, c->s));
+  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd[i].m, phis[i], prec64);
+  HIPCHK(hipGetLastError());
+
+  // profile: an event pair around the last-axis pass of every evaluation
+  std::vector<hipEvent_t> pev;
+  if (o.profile) {
+    pev.resize(2 * (size_t)o.chunk, nullptr);
+    for (auto& e : pev) HIPCHK(hipEventCreate(&e));
+  }
+  auto enqueue_eval = [&](int k) {
+    if (dim == 1) {
+      if (o.profile) (void)hipEventRecord(pev[2 * k], c->s);
+      launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), threads, smem[0], P, S, (const int2*)dbm[0],
+                         c->twd, c->twf);
+      if (o.profile) (void)hipEventRecord(pev[2 * k + 1], c->s);
+    } else {
+      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), threads, smem[0], P, S, (const int2*)dbm[0],
+                         c->twd, c->twf);
+      if (dim == 3)
+        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), threads, smem[1], P, S, (const int2*)dbm[1],
+                           c->twd, c->twf);
+      if (o.profile) (void)hipEventRecord(pev[2 * k], c->s);
+      launch_solver_pass(c->s, R_FINAL, prec64, (int)bm[dim - 1].size(), threads, smem[dim - 1], P, S,
+                         (const int2*)dbm[dim - 1], c->twd, c->twf);
+      if (o.profile) (void)hipEventRecord(pev[2 * k + 1], c->s);
+    }
+    launch_step(c->s, count, P, S, prec64);
+  };
+  auto free_events = [&]() {
+    for (auto& e : pev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (o.use_graph) {
+    HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < o.chunk; ++k) enqueue_eval(k);
+    HIPCHK(hipStreamEndCapture(c->s, &graph));
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  double pass_ms = 0.0;
+  int64_t pass_n = 0;
+  void* pin;
+  CHK(pinned_get(c, sizeof(SolverState) * count, &pin));
+  const int64_t cap = eval_cap(o);
+  int64_t evals = 0;
+  int rc = GPE_OK;
+  for (;;) {
+    if (exec) {
+      if (hipGraphLaunch(exec, c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
+    } else {
+      for (int k = 0; k < o.chunk; ++k) enqueue_eval(k);
+    }
+    evals += o.chunk;
+    if (hipMemcpyAsync(pin, dstate, sizeof(SolverState) * count, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipStreamSynchronize(c->s) != hipSuccess) {
+      rc = GPE_EDEVICE;
+      break;
+    }
+    const SolverState* hs = (const SolverState*)pin;
+    bool all = true;
+    int64_t maxnfe = 0;
+    for (int i = 0; i < count; ++i) {
+      all = all && hs[i].done;
+      maxnfe = std::max<int64_t>(maxnfe, hs[i].nfe);
+    }
+    if (o.profile) {
+      // launches of this chunk during which some problem was still active
+      const int64_t act = std::min<int64_t>(o.chunk, std::max<int64_t>(0, maxnfe - (evals - o.chunk)));
+      for (int64_t k = 0; k < act; ++k) {
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, pev[2 * k], pev[2 * k + 1]) == hipSuccess) {
+          pass_ms += e;
+          ++pass_n;
+        }
+      }
+    }
+    if (all) break;
+    if (evals > cap) { rc = GPE_NOT_CONVERGED; break; }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  free_events();
+  if (rc == GPE_EDEVICE) {
+    g_last_error = std::string("solver loop: ") + hipGetErrorString(hipGetLastError());
+    return rc;
+  }
+  HIPCHK(hipEventRecord(c->t1, c->s));
+  std::memcpy(st.data(), pin, sizeof(SolverState) * count);
+  for (int i = 0; i < count; ++i) launch_write_phi(c->s, P, S, i, pd[i].m, phis[i], prec64);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->s));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
+  int worst = GPE_OK;
+  for (int i = 0; i < count; ++i) {
+    gpe_result& r = results[i];
+    std::memset(&r, 0, sizeof(r));
+    const SolverState& s = st[i];
+    r.status = s.done ? s.status : GPE_NOT_CONVERGED;
+    r.outer_iters = s.outer;
+    r.inner_iters = s.inner_total;
+    r.nfe = s.nfe;
+    r.nfe_fp64 = s.nfe64;
+    r.backtracks = s.backtracks;
+    r.rejections = s.rejections;
+    r.delta = s.delta;
+    r.time_ms = ms;
+    r.nfe_f = s.nfe_f;
+    r.nfe_w = s.nfe_w;
+    r.nfe_outer = s.nfe_o;
+    r.pass_launches = (int32_t)pass_n;
+    r.pass_ms = pass_ms;
+    if (r.status >= 0) {
+      // outputs recomputed in float64 from the returned phi
+      double sc[10];
+      ApplyArgs a{0, 0.0, phis[i], nullptr, nullptr};
+      void* hout;
+      CHK(ws_get(c, WS_SCRATCH_OUT, (size_t)pd[i].m * 16, &hout));
+      a.out = hout;
+      CHK(run_apply(c, &probs[i], 1, a, sc));
+      r.energy = sc[0];
+      r.mu = sc[1];
+      r.resid = sc[2];
+      r.norm_err = sc[3] - 1.0;
+      r.rms[0] = sc[4]; r.rms[1] = sc[5]; r.rms[2] = sc[6];
+      r.max_dens = sc[7];
+      if (!std::isfinite(r.energy) || !std::isfinite(r.resid)) r.status = GPE_ENONFINITE;
+    }
+    if (r.status < 0 && worst >= 0) worst = r.status;
+    else if (r.status == GPE_NOT_CONVERGED && worst == GPE_OK) worst = GPE_NOT_CONVERGED;
+  }
+  if (rc == GPE_NOT_CONVERGED && worst == GPE_OK) worst = GPE_NOT_CONVERGED;
+  CHK(end_call(c));
+  return worst;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported
+// ===========================================================================
+extern "C" {
+
+void gpe_options_default(gpe_options* o) {
+  if (o) set_default(o);
+}
+
+const char* gpe_strerror(int status) {
+  switch (status) {
+    case GPE_OK: return "ok";
+    case GPE_NOT_CONVERGED: return "not converged (iteration cap)";
+    case GPE_EINVAL: return "invalid argument";
+    case GPE_EUNSUPPORTED: return "unsupported size or combination";
+    case GPE_ENOMEM: return "device allocation failed";
+    case GPE_EDEVICE: return "HIP runtime error";
+    case GPE_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* gpe_last_error(void) { return g_last_error.c_str(); }
+
+int gpe_ctx_create(gpe_ctx** out, int device, void* stream) {
+  if (!out) return GPE_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return GPE_EINVAL;
+  HIPCHK(hipSetDevice(device));
+  gpe_ctx* c = new gpe_ctx();
+  c->device = device;
+  c->user = (hipStream_t)stream;
+  int rc = GPE_OK;
+  do {
+    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) { rc = GPE_EDEVICE; break; }
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess) { rc = GPE_EDEVICE; break; }
+    // twiddle tables exp(-2 pi i m / 1024), float64 and float32
+    std::vector<double> twd(2 * kTwN);
+    std::vector<float> twf(2 * kTwN);
+    for (int m = 0; m < kTwN; ++m) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)kTwN;
+      const double cr = (double)std::cos(ang), ci = (double)std::sin(ang);
+      twd[2 * m] = cr; twd[2 * m + 1] = ci;
+      twf[2 * m] = (float)cr; twf[2 * m + 1] = (float)ci;
+    }
+    if (hipMalloc(&c->twd, twd.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->twf, twf.size() * sizeof(float)) != hipSuccess) { rc = GPE_ENOMEM; break; }
+    if (hipMemcpy(c->twd, twd.data(), twd.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->twf, twf.data(), twf.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = GPE_EDEVICE;
+      break;
+    }
+  } while (false);
+  if (rc != GPE_OK) {
+    g_last_error = std::string("context creation: ") + hipGetErrorString(hipGetLastError());
+    gpe_ctx_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return GPE_OK;
+}
+
+int gpe_ctx_destroy(gpe_ctx* c) {
+  if (!c) return GPE_OK;
+  (void)hipSetDevice(c->device);
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  for (int i = 0; i < WS_COUNT; ++i)
+    if (c->ws[i]) (void)hipFree(c->ws[i]);
+  if (c->twd) (void)hipFree(c->twd);
+  if (c->twf) (void)hipFree(c->twf);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->t0) (void)hipEventDestroy(c->t0);
+  if (c->t1) (void)hipEventDestroy(c->t1);
+  if (c->s) (void)hipStreamDestroy(c->s);
+  delete c;
+  return GPE_OK;
+}
+
+int gpe_apply_h(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const void* phi, void* h_phi,
+                double* scalars) {
+  if (!c || !prob || !phi || !h_phi || phi == h_phi) return GPE_EINVAL;
+  if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
+  CHK(begin_call(c));
+  ApplyArgs a{0, 0.0, phi, nullptr, h_phi};
+  CHK(run_apply(c, prob, precision == GPE_PREC_FP64, a, scalars));
+  return end_call(c);
+}
+
+int gpe_hess_vec(gpe_ctx* c, const gpe_problem* prob, const void* x_k, const void* s, double delta, void* out) {
+  if (!c || !prob || !x_k || !s || !out || out == s || out == x_k) return GPE_EINVAL;
+  CHK(begin_call(c));
+  ApplyArgs a{1, delta, s, x_k, out};
+  CHK(run_apply(c, prob, 1, a, nullptr));
+  return end_call(c);
+}
+
+int gpe_retract(gpe_ctx* c, int64_t m, const void* x, const void* g, double tau, void* y, double* coeffs) {
+  if (!c || m < 1 || !x || !g || !y || y == x || y == g) return GPE_EINVAL;
+  CHK(begin_call(c));
+  const int nblk = (int)std::min<int64_t>((m + 255) / 256, 1024);
+  void* part;
+  CHK(ws_get(c, WS_RETRACT, (size_t)nblk * 3 * sizeof(double) + 64, &part));
+  double* coef_dev = (double*)part + (size_t)nblk * 3;
+  launch_retract(c->s, nblk, x, g, y, m, tau, (double*)part, coef_dev);
+  HIPCHK(hipGetLastError());
+  if (coeffs) {
+    void* pin;
+    CHK(pinned_get(c, 64, &pin));
+    HIPCHK(hipMemcpyAsync(pin, coef_dev, 5 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    std::memcpy(coeffs, pin, 5 * sizeof(double));
+  }
+  return end_call(c);
+}
+
+int gpe_solve(gpe_ctx* c, const gpe_problem* prob, const gpe_options* opts, void* phi, gpe_result* result) {
+  void* phis[1] = {phi};
+  return solve_impl(c, 1, prob, opts, phis, result);
+}
+
+int gpe_solve_batched(gpe_ctx* c, int32_t count, const gpe_problem* probs, const gpe_options* opts,
+                      void* const* phis, gpe_result* results) {
+  return solve_impl(c, count, probs, opts, phis, results);
+}
+
+int gpe_prolong(gpe_ctx* c, const gpe_problem* coarse, const gpe_problem* fine, const void* phi_c, void* phi_f) {
+  if (!c || !coarse || !fine || !phi_c || !phi_f || phi_c == phi_f) return GPE_EINVAL;
+  ProbDev dc, df;
+  CHK(build_prob(coarse, &dc, nullptr));
+  CHK(build_prob(fine, &df, nullptr));
+  if (dc.dim != df.dim) return GPE_EINVAL;
+  for (int i = 0; i < dc.dim; ++i)
+    if (df.n[i] != 2 * dc.n[i] || coarse->lo[i] != fine->lo[i] || coarse->hi[i] != fine->hi[i]) return GPE_EINVAL;
+  CHK(begin_call(c));
+  int n[3] = {dc.n[0], dc.n[1], dc.n[2]};
+  const void* src = phi_c;
+  for (int ax = 0; ax < dc.dim; ++ax) {
+    void* dst;
+    if (ax == dc.dim - 1) dst = phi_f;
+    else {
+      int nn[3] = {n[0], n[1], n[2]};
+      nn[ax] *= 2;
+      CHK(ws_get(c, ax == 0 ? WS_PROLONG0 : WS_PROLONG1, (size_t)nn[0] * nn[1] * nn[2] * 16, &dst));
+    }
+    launch_prolong_axis(c->s, src, dst, n[0], n[1], n[2], ax, c->twd);
+    HIPCHK(hipGetLastError());
+    n[ax] *= 2;
+    src = dst;
+  }
+  return end_call(c);
+}
+
+int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int32_t nlevels, double level_tol,
+                       const gpe_options* opts, void* const* phi0s, void* const* phis, gpe_result* results) {
+  if (!c || count < 1 || !coarse || nlevels < 1 || !opts || !phi0s || !phis || !results) return GPE_EINVAL;
+  std::vector<gpe_problem> lev(coarse, coarse + count);
+  // per-level buffers: two ping-pong sets of `count` complex128 arrays
+  size_t maxm = 0;
+  for (int i = 0; i < count; ++i) {
+    size_t m = 1;
+    for (int a = 0; a < coarse[i].dim; ++a) m *= (size_t)coarse[i].n[a] << (nlevels - 1);
+    maxm = std::max(maxm, m);
+  }
+  void *b0, *b1;
+  CHK(ws_get(c, WS_LEVEL0, maxm * 16 * count, &b0));
+  CHK(ws_get(c, WS_LEVEL1, maxm * 16 * count, &b1));
+  std::vector<void*> cur(count), nxt(count);
+  CHK(begin_call(c));
+  for (int i = 0; i < count; ++i) {
+    cur[i] = (char*)b0 + (size_t)i * maxm * 16;
+    nxt[i] = (char*)b1 + (size_t)i * maxm * 16;
+    size_t m = 1;
+    for (int a = 0; a < coarse[i].dim; ++a) m *= coarse[i].n[a];
+    HIPCHK(hipMemcpyAsync(cur[i], phi0s[i], m * 16, hipMemcpyDeviceToDevice, c->s));
+  }
+  CHK(end_call(c));
+  std::vector<gpe_result> tmp(count);
+  std::vector<int64_t> nfe(count, 0), nfe64(count, 0), outer(count, 0), inner(count, 0);
+  double tms = 0.0;
+  int rc = GPE_OK;
+  for (int l = 0; l < nlevels; ++l) {
+    gpe_options o = *opts;
+    if (l < nlevels - 1) o.tol = level_tol;
+    std::vector<void*> dst(count);
+    for (int i = 0; i < count; ++i) dst[i] = (l == nlevels - 1) ? phis[i] : cur[i];
+    if (l == nlevels - 1)
+      for (int i = 0; i < count; ++i) {
+        size_t m = 1;
+        for (int a = 0; a < lev[i].dim; ++a) m *= lev[i].n[a];
+        CHK(begin_call(c));
+        HIPCHK(hipMemcpyAsync(phis[i], cur[i], m * 16, hipMemcpyDeviceToDevice, c->s));
+        CHK(end_call(c));
+      }
+    rc = solve_impl(c, count, lev.data(), &o, dst.data(), tmp.data());
+    if (rc < 0) return rc;
+    for (int i = 0; i < count; ++i) {
+      nfe[i] += tmp[i].nfe; nfe64[i] += tmp[i].nfe_fp64;
+      outer[i] += tmp[i].outer_iters; inner[i] += tmp[i].inner_iters;
+    }
+    tms += tmp[0].time_ms;
+    if (l < nlevels - 1) {
+      for (int i = 0; i < count; ++i) {
+        gpe_problem fine = lev[i];
+        for (int a = 0; a < fine.dim; ++a) fine.n[a] *= 2;
+        CHK(gpe_prolong(c, &lev[i], &fine, cur[i], nxt[i]));
+        lev[i] = fine;
+      }
+      std::swap(cur, nxt);
+    }
+  }
+  for (int i = 0; i < count; ++i) {
+    results[i] = tmp[i];
+    results[i].nfe = (int32_t)nfe[i];
+    results[i].nfe_fp64 = (int32_t)nfe64[i];
+    results[i].outer_iters = (int32_t)outer[i];
+    results[i].inner_iters = (int32_t)inner[i];
+    results[i].time_ms = tms;
+  }
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// H(phi) phi and the Newton-model Hessian-vector product as stand-alone
+// launch sequences (x pass, [y pass], last pass), sharing the line transforms
+// of the solver passes.
+#pragma once
+#include "passes_impl.h"
+
+namespace gpe {
+
+template <int N, int ROLE, typename T>
+__device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A, int tile, cx<T>* lds,
+                                           const cx<T>* tw, double* red) {
+  constexpr int E = Tile<N>::E;
+  const int ax = role_axis(ROLE, P.dim);
+  const Tile<N> Tl(P, ax, ROLE == R_MID || ROLE == R_FINAL, tile);
+  const cx<T>* in = reinterpret_cast<const cx<T>*>(A.in);
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = Tl.act ? in[Tl.g(e)] : cx<T>{0, 0};
+  spectral_apply<N, T>(P, ax, Tl, v, lds, tw);
+  cx<T>* tacc = reinterpret_cast<cx<T>*>(P.t);
+  if constexpr (ROLE == R_FIRST) {
+    if (Tl.act)
+#pragma unroll
+      for (int e = 0; e < E; ++e) tacc[Tl.g(e)] = v[e];
+  } else if constexpr (ROLE == R_MID) {
+    if (Tl.act)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t g = Tl.g(e);
+        tacc[g] = tacc[g] + v[e];
+      }
+  } else {
+    double acc[SA_COUNT] = {};
+    cx<T>* out = reinterpret_cast<cx<T>*>(A.out);
+    __syncthreads();  // LDS free again: stage the spectral results per thread
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[Tl.mp.idx(Tl.lane, Tl.t + e * Tl.TL, N)] = v[e];
+    if (Tl.act)
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int64_t g = Tl.g(e);
+        cx<double> kin = cvt<double>(lds[Tl.mp.idx(Tl.lane, Tl.t + e * Tl.TL, N)]);
+        if constexpr (ROLE == R_FINAL) kin = kin + cvt<double>(tacc[g]);
+        const cx<double> u = cvt<double>(in[g]);
+        const double vg = potential_at(P, g);
+        const double q = abs2(u);
+        if (A.kind == 0) {
+          const cx<double> h = kin + vg * u + (P.beta * q) * u;
+          out[g] = cvt<T>(h);
+          acc[SA_KIN] += redot(u, kin);
+          acc[SA_POT] += vg * q;
+          acc[SA_QUART] += q * q;
+          acc[SA_NORM] += q;
+          const int64_t ix = g % P.n[0];
+          const double x = P.lo[0] + P.h[0] * (double)ix;
+          acc[SA_X2] += x * x * q;
+          if (P.dim > 1) {
+            const double y = P.lo[1] + P.h[1] * (double)((g / P.n[0]) % P.n[1]);
+            acc[SA_Y2] += y * y * q;
+          }
+          if (P.dim > 2) {
+            const double z = P.lo[2] + P.h[2] * (double)(g / P.stride[2]);
+            acc[SA_Z2] += z * z * q;
+          }
+          acc[SA_MAXD] = fmax(acc[SA_MAXD], q);
+        } else {
+          const cx<double> x0 = reinterpret_cast<const cx<double>*>(A.xk)[g];
+          const cx<double> hs = 2.0 * (kin + vg * u) +
+                                (4.0 * P.alpha) * (abs2(x0) * u + (2.0 * redot(x0, u)) * x0) + A.delta * u;
+          out[g] = cvt<T>(hs);
+        }
+      }
+    block_reduce<SA_COUNT_SUM, 1>(acc, red);
+    if (threadIdx.x == 0) {
+      double* o = P.partF + (int64_t)tile * SA_COUNT;
+#pragma unroll
+      for (int i = 0; i < SA_COUNT; ++i) o[i] = acc[i];
+    }
+  }
+}
+
+template <int ROLE, typename T>
+__global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ probs, ApplyArgs A,
+                                                    const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[SA_COUNT * 16];
+  const ProbDev& P = probs[0];
+  const int tile = blockIdx.x;
+  const int n = P.n[role_axis(ROLE, P.dim)];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  switch (n) {
+    case 16: apply_tile<16, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 32: apply_tile<32, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 64: apply_tile<64, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 128: apply_tile<128, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 256: apply_tile<256, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 512: apply_tile<512, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 1024: apply_tile<1024, ROLE, T>(P, A, tile, lds, tw, red); break;
+    default: break;
+  }
+}
+
+}  // namespace gpe

@@ -1,0 +1,268 @@
+// Device building blocks: complex arithmetic, in-register/LDS Stockham FFT
+// for one line per group of threads, FP64 block reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "gpe_state.h"
+
+namespace gpe {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // a * conj(b)
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T> __device__ __forceinline__ T abs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T> __device__ __forceinline__ T redot(cx<T> a, cx<T> b) { return a.re * b.re + a.im * b.im; }  // Re(conj(a) b)
+template <typename To, typename Ti> __device__ __forceinline__ cx<To> cvt(cx<Ti> a) { return {(To)a.re, (To)a.im}; }
+
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename T> __device__ __forceinline__ cx<T> rot90(cx<T> a) {
+  return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers, y_k = sum_n x_n w^{nk}, w = exp(-+ 2 pi i / R).
+// ---------------------------------------------------------------------------
+template <bool INV, typename T>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> t = a - b;
+  a = a + b;
+  b = t;
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4(cx<T>& x0, cx<T>& x1, cx<T>& x2, cx<T>& x3) {
+  cx<T> a0 = x0 + x2, a1 = x0 - x2, a2 = x1 + x3, a3 = rot90<INV>(x1 - x3);
+  x0 = a0 + a2;
+  x2 = a0 - a2;
+  x1 = a1 + a3;
+  x3 = a1 - a3;
+}
+
+// multiply by w8^j, w8 = exp(-+ i pi/4)
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> tw8(cx<T> a, int j) {
+  const T s = (T)0.70710678118654752440;
+  switch (j & 7) {
+    case 0: return a;
+    case 1: return INV ? cx<T>{s * (a.re - a.im), s * (a.re + a.im)} : cx<T>{s * (a.re + a.im), s * (a.im - a.re)};
+    case 2: return rot90<INV>(a);
+    case 3: return INV ? cx<T>{-s * (a.re + a.im), s * (a.re - a.im)} : cx<T>{s * (a.im - a.re), -s * (a.re + a.im)};
+    default: return a;  // not used
+  }
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  o1 = tw8<INV>(o1, 1);
+  o2 = tw8<INV>(o2, 2);
+  o3 = tw8<INV>(o3, 3);
+  v[0] = e0 + o0; v[4] = e0 - o0;
+  v[1] = e1 + o1; v[5] = e1 - o1;
+  v[2] = e2 + o2; v[6] = e2 - o2;
+  v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+// multiply by w16^j for j in 0..9 (products n2*k1 of the 4x4 split)
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> tw16(cx<T> a, int j) {
+  // cos/sin of 2 pi j / 16
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+  const T r2 = (T)0.70710678118654752440;
+  T c, s;
+  switch (j) {
+    case 0: return a;
+    case 1: c = c1; s = s1; break;
+    case 2: c = r2; s = r2; break;
+    case 3: c = s1; s = c1; break;
+    case 4: return rot90<INV>(a);
+    case 6: c = -r2; s = r2; break;
+    case 9: c = -c1; s = -s1; break;
+    default: c = 1; s = 0; break;  // not used
+  }
+  // forward: multiply by (c - i s); inverse: (c + i s)
+  if (INV) return cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+  return cx<T>{a.re * c + a.im * s, a.im * c - a.re * s};
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+  cx<T> z[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cx<T> a = v[n2], b = v[4 + n2], c = v[8 + n2], d = v[12 + n2];
+    dft4<INV>(a, b, c, d);
+    z[n2][0] = a; z[n2][1] = b; z[n2][2] = c; z[n2][3] = d;
+  }
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) z[n2][k1] = tw16<INV>(z[n2][k1], n2 * k1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a = z[0][k1], b = z[1][k1], c = z[2][k1], d = z[3][k1];
+    dft4<INV>(a, b, c, d);
+    v[k1] = a; v[k1 + 4] = b; v[k1 + 8] = c; v[k1 + 12] = d;
+  }
+}
+
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dftR(cx<T>* u) {
+  if constexpr (R == 2) dft2<INV>(u[0], u[1]);
+  else if constexpr (R == 4) dft4<INV>(u[0], u[1], u[2], u[3]);
+  else if constexpr (R == 8) dft8<INV>(u);
+  else dft16<INV>(u);
+}
+
+// ---------------------------------------------------------------------------
+// Line FFT plan: N points handled by TL threads holding E = N/TL values each.
+// Thread t holds v[e] = line[t + e*TL] before and after a transform.
+// Radix-16 stages, then one stage of the remaining factor; the inverse runs
+// the stages in reverse order so that the forward output stays in registers.
+// ---------------------------------------------------------------------------
+template <int N> struct Plan;
+template <> struct Plan<16>   { static constexpr int E = 16, NS = 1; static constexpr int R[1] = {16}; };
+template <> struct Plan<32>   { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 2}; };
+template <> struct Plan<64>   { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 4}; };
+template <> struct Plan<128>  { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 8}; };
+template <> struct Plan<256>  { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 16}; };
+template <> struct Plan<512>  { static constexpr int E = 16, NS = 3; static constexpr int R[3] = {16, 16, 2}; };
+template <> struct Plan<1024> { static constexpr int E = 16, NS = 3; static constexpr int R[3] = {16, 16, 4}; };
+
+// LDS addressing of a line element: `lane` is the line inside the tile,
+// `pos` the position on the line.  Contiguous tiles store lines one after
+// the other (padded one element per 16); strided tiles interleave the lanes
+// (lane fastest) to match the coalesced global layout.
+struct LdsMap {
+  int lanes;       // lines per tile
+  bool strided;
+  __device__ __forceinline__ int idx(int lane, int pos, int n) const {
+    if (strided) return pos * (lanes + 1) + lane;
+    int row = n + (n >> 4);
+    return lane * row + pos + (pos >> 4);
+  }
+};
+
+template <int N, int R, bool INV, bool LAST, typename T>
+__device__ __forceinline__ void stockham_stage(cx<T>* v, int t, int ns, int lane, const LdsMap& mp,
+                                               cx<T>* lds, const cx<T>* tw) {
+  constexpr int E = Plan<N>::E;
+  constexpr int TL = N / E;
+  constexpr int B = E / R;  // butterflies per thread
+  cx<T> out[E];
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const int j = t + i * TL;
+    const int k = j & (ns - 1);
+    cx<T> u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[i + r * B];
+    if (ns > 1) {
+      const int step = kTwN / (ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = tw[(r * k * step) & (kTwN - 1)];
+        u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
+      }
+    }
+    dftR<R, INV>(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) out[i + r * B] = u[r];
+    } else {
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[mp.idx(lane, base + r * ns, N)] = u[r];
+    }
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = out[e];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = lds[mp.idx(lane, t + e * TL, N)];
+  }
+}
+
+// Full line transform; every thread of the block must call it (barriers).
+// `fresh` = true when the LDS buffer was not read since the last barrier.
+template <int N, bool INV, typename T>
+__device__ __forceinline__ void line_fft(cx<T>* v, int t, int lane, const LdsMap& mp, cx<T>* lds,
+                                         const cx<T>* tw) {
+  using P = Plan<N>;
+  if constexpr (P::NS == 1) {
+    stockham_stage<N, P::R[0], INV, true>(v, t, 1, lane, mp, lds, tw);
+  } else if constexpr (P::NS == 2) {
+    constexpr int R0 = INV ? P::R[1] : P::R[0];
+    constexpr int R1 = INV ? P::R[0] : P::R[1];
+    __syncthreads();
+    stockham_stage<N, R0, INV, false>(v, t, 1, lane, mp, lds, tw);
+    stockham_stage<N, R1, INV, true>(v, t, R0, lane, mp, lds, tw);
+  } else {
+    constexpr int R0 = INV ? P::R[2] : P::R[0];
+    constexpr int R1 = P::R[1];
+    constexpr int R2 = INV ? P::R[0] : P::R[2];
+    __syncthreads();
+    stockham_stage<N, R0, INV, false>(v, t, 1, lane, mp, lds, tw);
+    __syncthreads();
+    stockham_stage<N, R1, INV, false>(v, t, R0, lane, mp, lds, tw);
+    stockham_stage<N, R2, INV, true>(v, t, R0 * R1, lane, mp, lds, tw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions: wavefront butterfly, then across the block's waves.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Reduce NS sums followed by NM maxima over the block; thread 0 gets results
+// in `acc`.  `red` is LDS scratch of at least (NS+NM)*16 doubles.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce(double* acc, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) acc[i] = wave_sum(acc[i]);
+#pragma unroll
+  for (int i = NS; i < NS + NM; ++i) acc[i] = wave_max(acc[i]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NS + NM; ++i) red[i * 16 + wave] = acc[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NS + NM; ++i) {
+      double s = red[i * 16];
+      for (int w = 1; w < nw; ++w) s = (i < NS) ? s + red[i * 16 + w] : fmax(s, red[i * 16 + w]);
+      acc[i] = s;
+    }
+  }
+}
+
+}  // namespace gpe

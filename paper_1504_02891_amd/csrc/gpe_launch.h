@@ -1,0 +1,25 @@
+// Host-side launchers of the device kernels (one translation unit each).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+#include "gpe_state.h"
+
+namespace gpe {
+void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int threads, size_t smem,
+                        const ProbDev* probs, const SolverState* st, const int2* bmap,
+                        const void* twd, const void* twf);
+void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
+                       const ProbDev* probs, const ApplyArgs& a, const void* tw);
+void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64);
+void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64);
+void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
+                      int prec64);
+void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const void* phi, const void* hphi,
+                        double* rpart, int fp64);
+void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* rpart, int nr, double* out);
+void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
+                    double* part, double* coeffs);
+void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
+                         const void* twd);
+}  // namespace gpe

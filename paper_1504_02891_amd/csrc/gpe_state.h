@@ -1,0 +1,108 @@
+// Plain structs shared by the host driver and the device kernels.
+#pragma once
+#include <stdint.h>
+
+namespace gpe {
+
+constexpr int kMaxN = 1024;          // largest points per axis
+constexpr int kTwN = 1024;           // twiddle table length: exp(-2 pi i m / 1024)
+
+// Reduction slots of the first pass of an evaluation (sums and one max).
+enum Slot1 { S1_NY = 0, S1_NP2, S1_COUNT_SUM, S1_RMAX = S1_COUNT_SUM, S1_COUNT };
+// Reduction slots of the final pass of a solver evaluation.
+enum SlotF {
+  SF_F = 0,   // f(Y): F in F-mode, f_W in W-mode
+  SF_A,       // Re(Y^* g_Y)
+  SF_NG,      // ||g_Y||^2
+  SF_NY,      // ||Y||^2 of the stored trial
+  SF_SS,      // ||S||^2,  S = Y - X_base
+  SF_SY,      // Re(S^* Y)
+  SF_SG,      // Re(S^* g_Y)
+  SF_SW0,     // Re(S^* W0)
+  SF_W0W0,    // ||W0||^2
+  SF_W0G,     // Re(W0^* g_Y)
+  SF_W0Y,     // Re(W0^* Y)
+  SF_ARED,    // actual reduction F(Z) - F(X_k) in difference form (W-mode)
+  SF_COUNT_SUM,
+  SF_SMAX = SF_COUNT_SUM,  // max |S_j|
+  SF_COUNT
+};
+// Reduction slots of apply_h (phi units).
+enum SlotA {
+  SA_KIN = 0, SA_POT, SA_QUART, SA_NORM, SA_X2, SA_Y2, SA_Z2, SA_COUNT_SUM,
+  SA_MAXD = SA_COUNT_SUM, SA_COUNT
+};
+
+// Roles of the directional passes of one evaluation.
+enum Role { R_FIRST = 0, R_MID = 1, R_FINAL = 2, R_SOLO = 3 };
+
+// Evaluation modes (what the next launch sequence computes for a problem).
+enum Mode : int32_t { M_IDLE = 0, M_F = 1, M_W = 2, M_OUTER = 3 };
+// Solver phases.
+enum Phase : int32_t { PH_INIT = 0, PH_ALG1 = 1, PH_OUTER = 2, PH_INNER = 3, PH_DONE = 4 };
+// Source of the point an M_OUTER evaluation starts from.
+enum OuterSrc : int32_t { SRC_XK = 0, SRC_XK_PLUS_S = 1, SRC_XF = 2 };
+
+// Per-problem description used on the device (read only in kernels).
+struct ProbDev {
+  int32_t dim;
+  int32_t n[3];
+  int64_t stride[3];     // element stride of each axis: 1, nx, nx*ny
+  int64_t m;             // number of grid points
+  int32_t tiles[3];      // tiles (blocks) per pass along axis 0, 1, 2
+  int32_t lanes[3];      // lines per tile in each pass
+  int32_t has_v;         // 1: read v_arr, 0: separable v_axis tables
+  int32_t pad0;
+  double lo[3], h[3], len[3];
+  double beta, omega, hvol, sqrt_hvol, alpha;
+  const double* v_arr;   // explicit V (float64), or null
+  const double* v_axis;  // [3][kMaxN]: V = v_axis[0][x] + v_axis[1][y] + v_axis[2][z]
+  // solver arrays (element type depends on precision, see api)
+  void* xf[2];           // Algorithm 1 on F: iterate X (ping-pong)
+  void* gf[2];           // ... and its gradient
+  void* s[2];            // Newton subproblem: S = X - X_k (ping-pong)
+  void* d[2];            // ... and grad_W - G_k
+  void* xk;              // outer iterate X_k (complex double)
+  void* gk;              // G_k = grad F(X_k) (complex double)
+  void* t;               // accumulator of the directional passes (complex double sized)
+  double* part1;         // [tiles[0]][S1_COUNT]
+  double* partF;         // [tiles[dim-1]][SF_COUNT]
+  const void* user_in;   // apply / init input
+  void* user_out;        // apply output
+};
+
+// Per-problem solver state, written only by the step kernel.
+struct SolverState {
+  int32_t mode, phase, status, cur;       // cur: ping-pong index of xf/gf or s/d
+  int32_t src, force_norm, alg, done;
+  int32_t k, m, maxit, outer;
+  int32_t nfe, nfe64, inner_total, backtracks;
+  int32_t rejections, max_outer, nfe_f, nfe_w;
+  int32_t nfe_o, pad1, pad2, pad3;
+  // trial coefficients of the retraction, Y = p X_b + q g_b (pm1 = p - 1)
+  double p, q, pm1, t;
+  // scalars of the current base point
+  double f_b, a_b, n_b, ng_b;
+  double np2_b;                            // ||P_b||^2 of the base (first trial)
+  double n_hat;                            // c^2 ||Y_pre||^2 used in W0 (set by final pass rule)
+  double C, Q, tau_bb, tau_last;
+  double delta, forcing, f_outer, r_outer;
+  double pred_acc, ared_acc;               // model and actual reduction of the accepted inner iterate
+  double ss, sw, ww;                       // BB products of the last accepted step
+  // options copy
+  double tol, tau0, rho1, eta, sigma, renorm_tol;
+  double eta1, eta2, gshrink, ggrow, delta_min, delta_max;
+  int32_t k_init, k_sub, m_max, max_iter;
+};
+
+// Arguments of the stand-alone apply passes.
+// kind 0: H(phi) phi in phi units; kind 1: Hessian-vector product in X units.
+struct ApplyArgs {
+  int32_t kind;
+  double delta;            // Hessian-vector: regularisation delta
+  const void* in;          // phi (kind 0) or s (kind 1)
+  const void* xk;          // kind 1: X_k (complex double)
+  void* out;
+};
+
+}  // namespace gpe

@@ -1,0 +1,22 @@
+// One solver pass (role GPE_ROLE, precision GPE_PREC64) per object file, so
+// the build compiles the pass variants in parallel.
+#include "gpe_launch.h"
+#include "passes_impl.h"
+
+#ifndef GPE_ROLE
+#error "GPE_ROLE must be defined (0 first, 1 mid, 2 final, 3 solo)"
+#endif
+#ifndef GPE_PREC64
+#error "GPE_PREC64 must be defined (0 or 1)"
+#endif
+#define GPE_CAT2(a, b, c) a##b##_##c
+#define GPE_CAT(a, b, c) GPE_CAT2(a, b, c)
+
+namespace gpe {
+void GPE_CAT(launch_solver_pass_r, GPE_ROLE, GPE_PREC64)(hipStream_t s, int nblocks, int threads, size_t smem,
+                                                         const ProbDev* probs, const SolverState* st,
+                                                         const int2* bmap, const void* twd, const void* twf) {
+  hipLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0)>), dim3(nblocks), dim3(threads), smem, s, probs, st,
+                     bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+}
+}  // namespace gpe

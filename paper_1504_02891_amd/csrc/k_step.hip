@@ -1,0 +1,369 @@
+// Scalar control of the solver (one workgroup per problem, float64): the
+// nonmonotone BB line search of Algorithm 1 (§3.1) and the trust-region
+// ratio / regularisation update of Algorithm 2 (§3.2), plus the small
+// kernels around a solve (initial data, write-back, outputs, retraction,
+// prolongation).
+#include "gpe_launch.h"
+#include "passes_impl.h"
+
+namespace gpe {
+
+__device__ static void set_trial(SolverState& S) {
+  // Theorem 3.3 coefficients for the curve through the base point.
+  const double t = S.t, a = S.a_b, n = S.n_b, ng = S.ng_b;
+  const double den = 1.0 - t * t * a * a + t * t * n * ng;
+  S.p = ((1.0 + t * a) * (1.0 + t * a) - t * t * n * ng) / den;
+  S.q = -2.0 * t * n / den;
+  S.pm1 = 2.0 * t * (a + t * a * a - t * n * ng) / den;
+  S.mode = (S.phase == PH_INNER) ? M_W : M_F;
+}
+
+__device__ static void finish(SolverState& S, int status, int src) {
+  S.phase = PH_DONE;
+  S.mode = M_IDLE;
+  S.status = status;
+  S.src = src;
+  S.done = 1;
+}
+
+__device__ static void end_alg1(SolverState& S, bool stopped) {
+  if (S.alg == 1) {
+    finish(S, stopped ? 0 : 1, SRC_XF);
+    return;
+  }
+  S.tau_last = S.tau_bb;
+  S.phase = PH_OUTER;
+  S.mode = M_OUTER;
+  S.src = SRC_XF;
+  S.force_norm = 0;
+}
+
+__device__ static void end_inner(SolverState& S) {
+  const double pred = S.k > 0 ? S.pred_acc : 0.0;
+  const double rho = pred < 0.0 ? S.ared_acc / pred : -INFINITY;
+  const bool acc = rho >= S.eta1;
+  if (!acc) S.rejections++;
+  if (rho > S.eta2) S.delta *= S.gshrink;
+  else if (rho < S.eta1) S.delta *= S.ggrow;
+  S.delta = fmin(fmax(S.delta, S.delta_min), S.delta_max);
+  S.outer++;
+  S.tau_last = S.tau_bb;
+  S.phase = PH_OUTER;
+  S.mode = M_OUTER;
+  S.src = acc ? SRC_XK_PLUS_S : SRC_XK;
+  S.force_norm = acc ? 1 : 0;
+}
+
+__device__ static void step_logic(const ProbDev& P, SolverState& S, const double* r1, const double* rf,
+                                  int prec64) {
+  S.nfe++;
+  if (prec64 || S.mode == M_OUTER) S.nfe64++;
+  if (S.mode == M_F) S.nfe_f++;
+  else if (S.mode == M_W) S.nfe_w++;
+  else S.nfe_o++;
+  const double ny_pre = r1[S1_NY];
+  const double c = (S.force_norm || fabs(ny_pre - 1.0) > S.renorm_tol) ? 1.0 / sqrt(ny_pre) : 1.0;
+  const double n_hat = c * c * ny_pre;
+  if (S.phase == PH_INIT && ny_pre == 0.0) {   // zero initial data
+    finish(S, -1, SRC_XF);
+    return;
+  }
+  if (!isfinite(ny_pre) || !isfinite(rf[SF_F]) || !isfinite(rf[SF_NG]) || !isfinite(rf[SF_A]) ||
+      !isfinite(r1[S1_NP2]) || !(ny_pre > 0.0)) {
+    finish(S, -5, S.phase == PH_ALG1 || S.phase == PH_INIT ? SRC_XF : SRC_XK);
+    return;
+  }
+  const double rscale = 1.0 / (2.0 * P.sqrt_hvol);
+
+  if (S.phase == PH_INIT) {
+    S.f_b = rf[SF_F]; S.a_b = rf[SF_A]; S.n_b = rf[SF_NY]; S.ng_b = rf[SF_NG];
+    S.cur ^= 1;
+    S.C = S.f_b; S.Q = 1.0;
+    S.k = 0; S.m = 0;
+    S.tau_bb = S.tau0;
+    S.force_norm = 0;
+    S.phase = PH_ALG1;
+    S.maxit = (S.alg == 1) ? S.max_iter : S.k_init;
+    if (S.maxit <= 0 && S.alg != 1) { end_alg1(S, false); return; }
+    S.t = 0.5 * S.tau_bb;
+    set_trial(S);
+    return;
+  }
+  if (S.phase == PH_OUTER) {
+    S.f_outer = rf[SF_F];
+    S.a_b = rf[SF_A]; S.n_b = rf[SF_NY]; S.ng_b = rf[SF_NG]; S.f_b = 0.0;
+    S.k = 0; S.m = 0; S.C = 0.0; S.Q = 1.0;
+    S.tau_bb = S.tau_last;
+    S.cur = 0;
+    S.force_norm = 0;
+    S.phase = PH_INNER;
+    S.maxit = S.k_sub;
+    S.t = 0.5 * S.tau_bb;
+    set_trial(S);
+    return;
+  }
+  // PH_ALG1 / PH_INNER: a trial from the current base was evaluated.
+  if (S.m == 0) {
+    S.np2_b = r1[S1_NP2];
+    const double rb = r1[S1_RMAX] * rscale;   // residual of the base point (phi units)
+    if (S.phase == PH_ALG1) {
+      if (rb < S.tol) { end_alg1(S, true); return; }
+    } else {
+      if (S.k == 0) {
+        S.r_outer = rb;
+        if (rb < S.tol) { finish(S, 0, SRC_XK); return; }
+        if (S.outer >= S.max_outer) { finish(S, 1, SRC_XK); return; }
+        const double npk = sqrt(S.np2_b);
+        S.forcing = fmin(0.1, npk) * npk;
+      }
+      if (sqrt(S.np2_b) <= S.forcing) { end_inner(S); return; }
+    }
+  }
+  const bool pass = rf[SF_F] <= S.C - S.rho1 * S.t * S.np2_b;
+  if (pass || S.m >= S.m_max) {
+    const double ny = rf[SF_NY];
+    const double dn = ny - n_hat, da = rf[SF_A] - S.a_b;
+    S.ss = rf[SF_SS];
+    S.sw = rf[SF_SW0] + dn * rf[SF_SG] - da * rf[SF_SY];
+    S.ww = rf[SF_W0W0] + dn * dn * rf[SF_NG] + da * da * ny + 2.0 * dn * rf[SF_W0G] -
+           2.0 * da * rf[SF_W0Y] - 2.0 * dn * da * rf[SF_A];
+    S.f_b = rf[SF_F]; S.a_b = rf[SF_A]; S.n_b = ny; S.ng_b = rf[SF_NG];
+    if (S.phase == PH_INNER) { S.pred_acc = rf[SF_F]; S.ared_acc = rf[SF_ARED]; }
+    S.cur ^= 1;
+    const double qn = S.eta * S.Q + 1.0;
+    S.C = (S.eta * S.Q * S.C + S.f_b) / qn;
+    S.Q = qn;
+    S.k++; S.inner_total++; S.m = 0;
+    if (S.k >= S.maxit) {
+      if (S.phase == PH_ALG1) end_alg1(S, false);
+      else end_inner(S);
+      return;
+    }
+    const double sw = fabs(S.sw);
+    if (sw > 0.0) S.tau_bb = (S.k & 1) ? S.ss / sw : sw / S.ww;
+    S.tau_bb = fmin(fmax(S.tau_bb, 1e-20), 1e20);
+    S.t = 0.5 * S.tau_bb;
+  } else {
+    S.m++;
+    S.backtracks++;
+    S.t *= S.sigma;
+  }
+  set_trial(S);
+}
+
+__global__ void __launch_bounds__(64) k_step(const ProbDev* __restrict__ probs, SolverState* states,
+                                             int prec64) {
+  __shared__ double red[4];
+  const ProbDev& P = probs[blockIdx.x];
+  SolverState& S = states[blockIdx.x];
+  if (S.mode == M_IDLE) return;
+  double r1[S1_COUNT], rf[SF_COUNT];
+#pragma unroll
+  for (int s = 0; s < S1_COUNT; ++s) r1[s] = fixed_reduce(P.part1, P.tiles[0], S1_COUNT, s, s == S1_RMAX, red);
+  const int tf = P.tiles[P.dim - 1];
+#pragma unroll
+  for (int s = 0; s < SF_COUNT; ++s) rf[s] = fixed_reduce(P.partF, tf, SF_COUNT, s, s == SF_SMAX, red);
+  if (threadIdx.x == 0) step_logic(P, S, r1, rf, prec64);
+}
+
+// ---- initial data: X_0 = sqrt(h_vol) phi_0 in the F-mode arrays, G = 0 ----
+template <typename TF>
+__global__ void k_init(const ProbDev* probs, int pi, const cx<double>* __restrict__ phi0) {
+  const ProbDev& P = probs[pi];
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
+    stc<TF>(P.xf[0], g, cvt<TF>(P.sqrt_hvol * phi0[g]));
+    stc<TF>(P.gf[0], g, cx<TF>{0, 0});
+  }
+}
+
+// ---- write phi = X / sqrt(h_vol) of the final iterate ----
+template <typename TF>
+__global__ void k_write_phi(const ProbDev* probs, const SolverState* states, int pi, cx<double>* __restrict__ phi) {
+  const ProbDev& P = probs[pi];
+  const SolverState& S = states[pi];
+  const double sc = 1.0 / P.sqrt_hvol;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
+    cx<double> x = (S.src == SRC_XF) ? cvt<double>(ld<TF>(P.xf[S.cur], g)) : reinterpret_cast<const cx<double>*>(P.xk)[g];
+    phi[g] = sc * x;
+  }
+}
+
+// ---- apply_h outputs: residual max |H phi - mu phi| and the scalar summary ----
+__device__ static void apply_energy(const ProbDev& P, double* red, double* kin, double* pot, double* quart) {
+  const int tf = P.tiles[P.dim - 1];
+  *kin = fixed_reduce(P.partF, tf, SA_COUNT, SA_KIN, false, red);
+  *pot = fixed_reduce(P.partF, tf, SA_COUNT, SA_POT, false, red);
+  *quart = fixed_reduce(P.partF, tf, SA_COUNT, SA_QUART, false, red);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply_resid(const ProbDev* probs, const cx<T>* __restrict__ phi,
+                                                     const cx<T>* __restrict__ hphi, double* __restrict__ rpart) {
+  __shared__ double red[16];
+  const ProbDev& P = probs[0];
+  double kin, pot, quart;
+  apply_energy(P, red, &kin, &pot, &quart);
+  const double e = P.hvol * (kin + pot + 0.5 * P.beta * quart);
+  const double mu = e + 0.5 * P.beta * P.hvol * quart;
+  double r = 0.0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
+    const cx<double> u = cvt<double>(phi[g]), h = cvt<double>(hphi[g]);
+    r = fmax(r, abs2(h - mu * u));
+  }
+  double acc[1] = {r};
+  block_reduce<0, 1>(acc, red);
+  if (threadIdx.x == 0) rpart[blockIdx.x] = acc[0];
+}
+
+__global__ void __launch_bounds__(64) k_apply_finalize(const ProbDev* probs, const double* __restrict__ rpart,
+                                                       int nr, double* __restrict__ out) {
+  __shared__ double red[4];
+  const ProbDev& P = probs[0];
+  double kin, pot, quart;
+  apply_energy(P, red, &kin, &pot, &quart);
+  const int tf = P.tiles[P.dim - 1];
+  double s[4];
+  s[0] = fixed_reduce(P.partF, tf, SA_COUNT, SA_NORM, false, red);
+  s[1] = fixed_reduce(P.partF, tf, SA_COUNT, SA_X2, false, red);
+  s[2] = fixed_reduce(P.partF, tf, SA_COUNT, SA_Y2, false, red);
+  s[3] = fixed_reduce(P.partF, tf, SA_COUNT, SA_Z2, false, red);
+  const double maxd = fixed_reduce(P.partF, tf, SA_COUNT, SA_MAXD, true, red);
+  const double rmax = fixed_reduce(rpart, nr, 1, 0, true, red);
+  if (threadIdx.x == 0) {
+    const double e = P.hvol * (kin + pot + 0.5 * P.beta * quart);
+    out[0] = e;
+    out[1] = e + 0.5 * P.beta * P.hvol * quart;
+    out[2] = sqrt(rmax);
+    out[3] = P.hvol * s[0];
+    out[4] = sqrt(P.hvol * s[1]);
+    out[5] = sqrt(P.hvol * s[2]);
+    out[6] = sqrt(P.hvol * s[3]);
+    out[7] = maxd;
+    out[8] = P.hvol * kin;
+    out[9] = P.hvol * pot;
+  }
+}
+
+// ---- Cayley retraction (Theorem 3.3) on plain vectors ----
+__global__ void __launch_bounds__(256) k_retract_reduce(const cx<double>* __restrict__ x, const cx<double>* __restrict__ g,
+                                                        int64_t m, double* __restrict__ part) {
+  __shared__ double red[3 * 16];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const cx<double> a = x[i], b = g[i];
+    acc[0] += redot(a, b);
+    acc[1] += abs2(a);
+    acc[2] += abs2(b);
+  }
+  block_reduce<3, 0>(acc, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 3 + 0] = acc[0];
+    part[blockIdx.x * 3 + 1] = acc[1];
+    part[blockIdx.x * 3 + 2] = acc[2];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_retract_apply(const cx<double>* __restrict__ x, const cx<double>* __restrict__ g,
+                                                       cx<double>* __restrict__ y, int64_t m, double tau,
+                                                       const double* __restrict__ part, int np,
+                                                       double* __restrict__ coeffs) {
+  __shared__ double red[4];
+  const double a = fixed_reduce(part, np, 3, 0, false, red);
+  const double nx = fixed_reduce(part, np, 3, 1, false, red);
+  const double ng = fixed_reduce(part, np, 3, 2, false, red);
+  const double den = 1.0 - tau * tau * a * a + tau * tau * nx * ng;
+  const double p = ((1.0 + tau * a) * (1.0 + tau * a) - tau * tau * nx * ng) / den;
+  const double q = -2.0 * tau * nx / den;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = p * x[i] + q * g[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    coeffs[0] = p; coeffs[1] = q; coeffs[2] = a; coeffs[3] = nx; coeffs[4] = ng;
+  }
+}
+
+// ---- trigonometric prolongation along one axis (n -> 2n points) ----
+// One workgroup per line; direct sums with the exact twiddle table.
+__global__ void __launch_bounds__(256) k_prolong_axis(const cx<double>* __restrict__ in, cx<double>* __restrict__ out,
+                                                      int n0, int n1, int n2, int ax,
+                                                      const cx<double>* __restrict__ tw) {
+  __shared__ cx<double> line[kMaxN / 2];
+  __shared__ cx<double> spec[kMaxN / 2];
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  const int64_t lines = (int64_t)n0 * n1 * n2 / n;
+  const int64_t L = blockIdx.x;
+  if (L >= lines) return;
+  // input strides and the line's base in the input and output arrays
+  int64_t bi, bo, si, so;
+  if (ax == 0) { bi = L * n0; bo = L * 2 * n0; si = 1; so = 1; }
+  else if (ax == 1) {
+    const int64_t x = L % n0, z = L / n0;
+    bi = z * (int64_t)n0 * n1 + x; bo = z * (int64_t)n0 * 2 * n1 + x; si = n0; so = n0;
+  } else { bi = L; bo = L; si = (int64_t)n0 * n1; so = (int64_t)n0 * n1; }
+  for (int j = threadIdx.x; j < n; j += blockDim.x) line[j] = in[bi + j * si];
+  __syncthreads();
+  const int stp = kTwN / n;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {   // c_p = sum_j f_j exp(-2 pi i p j / n)
+    cx<double> c{0.0, 0.0};
+    for (int j = 0; j < n; ++j) c = c + cmul(line[j], tw[((int64_t)p * j * stp) & (kTwN - 1)]);
+    spec[p] = c;
+  }
+  __syncthreads();
+  const int stf = kTwN / (2 * n);
+  const double inv = 1.0 / n;
+  for (int jf = threadIdx.x; jf < 2 * n; jf += blockDim.x) {
+    // (1/n) [ sum_{|p| < n/2} c_p e^{2 pi i p jf / 2n} + c_{n/2} cos(pi jf / 2) ]
+    cx<double> s{0.0, 0.0};
+    for (int p = -(n / 2) + 1; p < n / 2; ++p) {
+      const int pi = p < 0 ? p + n : p;
+      const int64_t k = ((int64_t)(p < 0 ? p + 2 * n : p) * jf * stf) & (kTwN - 1);
+      s = s + cmulc(spec[pi], tw[k]);   // spec * conj(exp(-...)) = spec * exp(+...)
+    }
+    const int jm = jf & 3;
+    const double cs = jm == 0 ? 1.0 : (jm == 2 ? -1.0 : 0.0);
+    s = s + cs * spec[n / 2];
+    out[bo + jf * so] = inv * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64) {
+  hipLaunchKernelGGL(k_step, dim3(nprob), dim3(64), 0, s, probs, st, prec64);
+}
+void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64) {
+  const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
+  if (prec64) hipLaunchKernelGGL(k_init<double>, dim3(blocks), dim3(256), 0, s, probs, pi, (const cx<double>*)phi0);
+  else hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, probs, pi, (const cx<double>*)phi0);
+}
+void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
+                      int prec64) {
+  const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
+  if (prec64) hipLaunchKernelGGL(k_write_phi<double>, dim3(blocks), dim3(256), 0, s, probs, st, pi, (cx<double>*)phi);
+  else hipLaunchKernelGGL(k_write_phi<float>, dim3(blocks), dim3(256), 0, s, probs, st, pi, (cx<double>*)phi);
+}
+void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const void* phi, const void* hphi,
+                        double* rpart, int fp64) {
+  if (fp64) hipLaunchKernelGGL(k_apply_resid<double>, dim3(nblk), dim3(256), 0, s, probs,
+                               (const cx<double>*)phi, (const cx<double>*)hphi, rpart);
+  else hipLaunchKernelGGL(k_apply_resid<float>, dim3(nblk), dim3(256), 0, s, probs,
+                          (const cx<float>*)phi, (const cx<float>*)hphi, rpart);
+}
+void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* rpart, int nr, double* out) {
+  hipLaunchKernelGGL(k_apply_finalize, dim3(1), dim3(64), 0, s, probs, rpart, nr, out);
+}
+void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
+                    double* part, double* coeffs) {
+  hipLaunchKernelGGL(k_retract_reduce, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, (const cx<double>*)g, m, part);
+  hipLaunchKernelGGL(k_retract_apply, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, (const cx<double>*)g,
+                     (cx<double>*)y, m, tau, part, nblk, coeffs);
+}
+void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
+                         const void* twd) {
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  const int64_t lines = (int64_t)n0 * n1 * n2 / n;
+  hipLaunchKernelGGL(k_prolong_axis, dim3((unsigned)lines), dim3(256), 0, s, (const cx<double>*)in, (cx<double>*)out,
+                     n0, n1, n2, ax, (const cx<double>*)twd);
+}
+
+}  // namespace gpe

@@ -1,0 +1,160 @@
+"""GPU parity of the primitives (H(phi)phi, Hessian-vector product, Cayley
+retraction, prolongation) against the oracle, through the C ABI.
+
+Tolerance of a spectral pass (rounding analysis of a radix-2^k FFT pair):
+|err| <= C * eps * log2(N) * (max|multiplier| + max|V| + beta max|phi|^2) * max|phi|,
+with eps the unit roundoff of the transform precision and C = 16 (FP64) or
+C = 32 (FP32); reductions accumulate in FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import discretization as disc
+from oracle.cascade import prolong_fourier
+from oracle.feasible import cayley_coefficients
+from oracle.unified import UnifiedProblem, re_dot
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = {"fp64": 2.0 ** -53, "mixed": 2.0 ** -24}
+CFAC = {"fp64": 16.0, "mixed": 32.0}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_02891_amd import api
+    return api
+
+
+def _bound(p, phi, prec):
+    """Rounding bound of one application of H (see the module docstring)."""
+    lam = [math.pi * p.n[a] / (p.hi[a] - p.lo[a]) for a in range(p.dim)]
+    rot = max(abs(p.omega) * max(abs(p.lo[b]), abs(p.hi[b])) for b in range(p.dim)) if p.dim > 1 else 0.0
+    mult = sum(0.5 * l * l + rot * l for l in lam)
+    vmax = float(np.max(disc.potential(p)))
+    amax = float(np.max(np.abs(phi)))
+    lg = max(math.log2(n) for n in p.n)
+    return CFAC[prec] * EPS[prec] * lg * (mult + vmax + p.beta * amax ** 2) * amax
+
+
+def _field(p, seed):
+    rng = np.random.default_rng(seed)
+    cs = disc.grid_coords(p)
+    r2 = sum(c * c for c in cs)
+    smooth = np.exp(-r2 / 4.0) * (1 + 0.5j * cs[0])
+    noise = 0.05 * (rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape))
+    phi = smooth + noise
+    return phi / math.sqrt(disc.h_vol(p) * float(np.sum(np.abs(phi) ** 2)))
+
+
+CASES = [
+    W.Problem(dim=1, n=(16,), lo=(-4.0,), hi=(4.0,), beta=10.0),
+    W.Problem(dim=1, n=(512,), lo=(-16.0,), hi=(16.0,), beta=400.0),
+    W.Problem(dim=1, n=(1024,), lo=(-20.0,), hi=(20.0,), beta=50.0, lattice_amp=25.0),
+    W.Problem(dim=2, n=(64, 32), lo=(-8.0, -6.0), hi=(8.0, 6.0), beta=300.0, omega=0.7),
+    W.Problem(dim=2, n=(16, 1024), lo=(-5.0, -20.0), hi=(5.0, 20.0), beta=100.0, omega=0.3),
+    W.Problem(dim=2, n=(256, 256), lo=(-12.0, -12.0), hi=(12.0, 12.0), beta=1000.0, omega=0.9),
+    W.Problem(dim=3, n=(32, 16, 64), lo=(-6.0, -5.0, -7.0), hi=(6.0, 5.0, 7.0), beta=200.0,
+              omega=0.4, gamma=(1.0, 1.5, 2.0), lattice_amp=10.0),
+    W.Problem(dim=3, n=(128, 128, 128), lo=(-16.0,) * 3, hi=(16.0,) * 3, beta=1600.0,
+              lattice_amp=100.0),
+]
+
+
+def _cid(p):
+    return f"d{p.dim}-" + "x".join(str(n) for n in p.n) + f"-om{p.omega}"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("p", CASES, ids=_cid)
+def test_apply_h_matches_oracle(dev, p, prec):
+    phi = _field(p, 1)
+    ref = disc.h_full(p, phi)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    t = torch.from_numpy(phi).to(dt).cuda()
+    out, sc = dev.apply_h(p, t, precision=prec)
+    got = out.cpu().numpy().astype(np.complex128)
+    phi_in = t.cpu().numpy().astype(np.complex128)     # the value the kernel saw
+    ref = disc.h_full(p, phi_in)
+    tol = _bound(p, phi_in, prec)
+    err = float(np.max(np.abs(got - ref)))
+    assert err <= tol, (err, tol)
+    up = UnifiedProblem(p)
+    o = up.outputs(up.to_x(phi_in))
+    rtol = 1e-11 if prec == "fp64" else 3e-6
+    assert abs(sc["energy"] - o["energy"]) <= rtol * abs(o["energy"])
+    assert abs(sc["mu"] - o["mu"]) <= rtol * abs(o["mu"])
+    assert abs(sc["norm2"] - up.hvol * float(np.sum(np.abs(phi_in) ** 2))) <= 1e-12
+    assert abs(sc["resid"] - o["resid"]) <= tol + rtol * o["resid"]
+    for a in range(p.dim):
+        assert abs(sc["rms_" + "xyz"[a]] - o["rms"][a]) <= rtol * o["rms"][a] + 1e-14
+    assert abs(sc["max_dens"] - o["max_dens"]) <= 1e-12 * o["max_dens"] + 1e-15
+
+
+def test_apply_h_gaussian_closed_form(dev):
+    # beta = 0, Omega = 0 harmonic trap: H phi = (d/2) phi exactly.
+    p = W.Problem(dim=2, n=(64, 128), lo=(-12.0, -12.0), hi=(12.0, 12.0))
+    x, y = disc.grid_coords(p)
+    g = np.exp(-(x * x + y * y) / 2) / math.sqrt(math.pi) + 0j
+    out, sc = dev.apply_h(p, torch.from_numpy(g).cuda())
+    assert float(np.max(np.abs(out.cpu().numpy() - g))) < 1e-11
+    assert abs(sc["energy"] - 1.0) < 1e-12 and sc["resid"] < 1e-11
+
+
+def test_apply_h_explicit_potential_array(dev):
+    p = W.Problem(dim=2, n=(32, 64), lo=(-6.0, -8.0), hi=(6.0, 8.0), beta=50.0, omega=0.5)
+    x, y = disc.grid_coords(p)
+    v = 0.5 * (x * x + 2 * y * y) + 4.0 * np.exp(-((x - 1) ** 2 + y * y))
+    q = W.Problem(dim=2, n=p.n, lo=p.lo, hi=p.hi, beta=p.beta, omega=p.omega, v=v)
+    phi = _field(p, 3)
+    out, _ = dev.apply_h(p, torch.from_numpy(phi).cuda(), v=torch.from_numpy(v).cuda())
+    ref = disc.h_full(q, phi)
+    assert float(np.max(np.abs(out.cpu().numpy() - ref))) <= _bound(q, phi, "fp64")
+
+
+@pytest.mark.parametrize("p", [CASES[1], CASES[3], CASES[6]], ids=_cid)
+def test_hess_vec_matches_oracle(dev, p):
+    up = UnifiedProblem(p)
+    xk = up.to_x(_field(p, 5))
+    s = 1e-2 * up.to_x(_field(p, 6))
+    delta = 0.37
+    ref = up.hess(xk, s) + delta * s
+    got = dev.hess_vec(p, torch.from_numpy(xk).cuda(), torch.from_numpy(s).cuda(), delta).cpu().numpy()
+    scale = 2 * _bound(p, s / math.sqrt(up.hvol), "fp64") * math.sqrt(up.hvol) \
+        + 1e-13 * float(np.max(np.abs(ref)))
+    assert float(np.max(np.abs(got - ref))) <= scale
+
+
+@pytest.mark.parametrize("m", [1, 255, 65536 + 17])
+def test_retract_matches_cayley_closed_form(dev, m):
+    rng = np.random.default_rng(m)
+    x = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    x /= np.linalg.norm(x)
+    g = 7.0 * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+    tau = 0.013
+    y, co = dev.retract(torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda(), tau)
+    a, nx, ng = re_dot(x, g), re_dot(x, x), re_dot(g, g)
+    p, q = cayley_coefficients(tau, a, nx, ng)
+    assert abs(co["p"] - p) < 1e-12 and abs(co["q"] - q) < 1e-12
+    yr = p * x + q * g
+    assert float(np.max(np.abs(y.cpu().numpy() - yr))) < 1e-12 * float(np.max(np.abs(yr)))
+    assert abs(np.linalg.norm(y.cpu().numpy()) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(32,), (16, 64), (64, 64), (256, 256), (16, 32, 16)])
+def test_prolong_matches_oracle(dev, dims):
+    d = len(dims)
+    pc = W.Problem(dim=d, n=dims, lo=(-5.0,) * d, hi=(7.0,) * d)
+    pf = pc.with_n(tuple(2 * n for n in dims))
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal(pc.shape) + 1j * rng.standard_normal(pc.shape)
+    got = dev.prolong(pc, pf, torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = prolong_fourier(u)
+    n = max(dims)
+    assert float(np.max(np.abs(got - ref))) < 1e-13 * n * float(np.max(np.abs(ref)))
