@@ -83,8 +83,14 @@ typedef struct gpe_options {
     double delta0, delta_min, delta_max;          /* regularisation delta */
     int32_t chunk;        /* evaluations per host check of the done flags (graph size) */
     int32_t use_graph;    /* 1: replay chunks as a captured hipGraph; 0: plain launches */
-    int32_t profile;      /* 1: time every launch of the last-axis pass with HIP events */
+    int32_t profile;      /* k > 0: time every k-th launch of the last-axis pass with HIP events
+                             (plain launches instead of a graph); 0: off */
     int32_t reserved0;
+    int32_t threads[3];   /* workgroup size of the x, y, z passes (0 = built-in choice);
+                             must be a multiple of n/8 and at most 256 */
+    int32_t separate_step;/* scalar step: 1 its own launch, 0 in the last workgroup of the
+                             final pass (a device-scope fence per workgroup), -1 automatic
+                             (fused only when the final pass is one workgroup per problem) */
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */
@@ -108,7 +114,7 @@ typedef struct gpe_result {
     int32_t nfe_f;        /* evaluations of F in Algorithm 1 (including the initial one) */
     int32_t nfe_w;        /* evaluations of the Newton model W */
     int32_t nfe_outer;    /* float64 evaluations of F at outer iterates */
-    int32_t pass_launches;/* profile: timed launches of the last-axis pass (solver active) */
+    int32_t pass_launches;/* profile: timed (sampled) launches of the last-axis pass */
     double pass_ms;       /* profile: summed event time of those launches */
 } gpe_result;
 

@@ -46,7 +46,7 @@ class Options(C.Structure):
                 ("gamma_grow", C.c_double),
                 ("delta0", C.c_double), ("delta_min", C.c_double), ("delta_max", C.c_double),
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("reserved0", C.c_int32), ("threads", C.c_int32 * 3), ("separate_step", C.c_int32)]
 
 
 class Result(C.Structure):

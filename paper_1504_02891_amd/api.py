@@ -77,6 +77,10 @@ def options(**kw):
     alg = kw.pop("algorithm", None)
     if alg is not None:
         o.algorithm = {"alg1": N.GPE_ALG1, "alg2": N.GPE_ALG2}.get(alg, alg)
+    thr = kw.pop("threads", None)
+    if thr is not None:
+        for i, t in enumerate(list(thr)[:3]):
+            o.threads[i] = int(t)
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")

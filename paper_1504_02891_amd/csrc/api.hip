@@ -178,18 +178,28 @@ struct Geom {
   size_t smem;
 };
 
-// Tiling of a pass along axis `ax`: lines of N = n[ax] points, TL = N/16
+// Tiling of a pass along axis `ax`: lines of N = n[ax] points, TL = N/kE
 // threads per line, `threads / TL` lines per workgroup.
 Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem) {
   Geom g;
   const int N = d.n[ax];
-  const int TL = N / 16;
+  const int TL = N / kE;
   g.threads = threads < TL ? TL : threads;
   g.lanes = g.threads / TL;
   const int64_t cols = d.m / N;
   g.tiles = (int)((cols + g.lanes - 1) / g.lanes);
-  g.smem = strided ? (size_t)N * (g.lanes + 1) * elem : (size_t)g.lanes * (N + N / 16) * elem;
+  // twiddle table (N entries) + line data
+  g.smem = ((size_t)N + (size_t)gpe::lds_elems_host(N, g.lanes, strided)) * elem;
   return g;
+}
+
+// Built-in workgroup size: one wavefront for 1D (a single line), 256 threads
+// once the problem is large enough to be bandwidth bound, else 128.
+int default_threads(const std::vector<ProbDev>& pd, int dim) {
+  if (dim == 1) return 64;
+  int64_t m = 0;
+  for (const ProbDev& d : pd) m += d.m;
+  return m >= ((int64_t)1 << 20) ? 256 : kSolverThreads;
 }
 
 void set_default(gpe_options* o) {
@@ -217,6 +227,8 @@ void set_default(gpe_options* o) {
   o->use_graph = 1;
   o->profile = 0;
   o->reserved0 = 0;
+  o->threads[0] = o->threads[1] = o->threads[2] = 0;
+  o->separate_step = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,7 +291,7 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
 // solver
 // ---------------------------------------------------------------------------
 struct ProbLayout {
-  size_t off_xf[2], off_gf[2], off_s[2], off_d[2], off_xk, off_gk, off_t, off_p1, off_pf;
+  size_t off_xf[2], off_gf[2], off_s[2], off_d[2], off_xk, off_gk, off_t, off_p1, off_pf, off_ticket;
 };
 
 void init_state(SolverState& S, const gpe_options& o) {
@@ -338,17 +350,33 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   // geometry of each pass for each problem
   std::vector<Geom> geo((size_t)count * 3);
   size_t smem[3] = {0, 0, 0};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int th = o.threads[ax];
+    if (th != 0 && (th < 1 || th > 256)) return GPE_EINVAL;
+    for (int i = 0; i < count && th != 0 && ax < dim; ++i)
+      if (th % (pd[i].n[ax] / kE) != 0) return GPE_EINVAL;
+  }
   for (int i = 0; i < count; ++i)
     for (int ax = 0; ax < dim; ++ax) {
-      Geom g = dim == 1 ? pass_geom(pd[i], 0, false, 64, 16) : pass_geom(pd[i], ax, ax > 0, kSolverThreads, 16);
+      const int th = o.threads[ax] ? o.threads[ax] : default_threads(pd, dim);
+      Geom g = pass_geom(pd[i], ax, ax > 0, th, 16);
       geo[(size_t)i * 3 + ax] = g;
       pd[i].tiles[ax] = g.tiles;
       pd[i].lanes[ax] = g.lanes;
       smem[ax] = std::max(smem[ax], g.smem);
     }
-  const int threads = dim == 1 ? geo[0].threads : kSolverThreads;
-  for (int i = 0; i < count; ++i)
-    if (dim == 1 && geo[(size_t)i * 3].threads != threads) return GPE_EUNSUPPORTED;  // 1D batch: one n
+  int thr[3] = {0, 0, 0};
+  for (int ax = 0; ax < dim; ++ax) {
+    thr[ax] = geo[ax].threads;
+    for (int i = 1; i < count; ++i)
+      if (geo[(size_t)i * 3 + ax].threads != thr[ax]) return GPE_EUNSUPPORTED;  // one workgroup size per pass
+  }
+  bool fuse = o.separate_step == 0;
+  if (o.separate_step < 0) {
+    fuse = true;
+    for (int i = 0; i < count; ++i) fuse = fuse && pd[i].tiles[dim - 1] == 1;
+  }
+  for (int i = 0; i < count; ++i) pd[i].fuse_step = fuse ? 1 : 0;
   // arena layout
   std::vector<ProbLayout> lay(count);
   size_t off = 0;
@@ -371,6 +399,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     L.off_t = take(m * 16);
     L.off_p1 = take((size_t)pd[i].tiles[0] * S1_COUNT * sizeof(double));
     L.off_pf = take((size_t)std::max(pd[i].tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
+    L.off_ticket = take(64);
   }
   CHK(begin_call(c));
   void *arena, *dprob, *dstate, *dvax, *dbm[3] = {nullptr, nullptr, nullptr};
@@ -393,6 +422,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     d.t = A + L.off_t;
     d.part1 = (double*)(A + L.off_p1);
     d.partF = (double*)(A + L.off_pf);
+    d.ticket = (int32_t*)(A + L.off_ticket);
     d.v_axis = (const double*)dvax + (size_t)i * 3 * kMaxN;
   }
   // block maps: (problem, tile) for each pass
@@ -427,24 +457,24 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     pev.resize(2 * (size_t)o.chunk, nullptr);
     for (auto& e : pev) HIPCHK(hipEventCreate(&e));
   }
+  int64_t eval_index = 0;   // evaluations enqueued so far (profile sampling)
+  auto sampled = [&](int64_t e) { return o.profile > 0 && e % o.profile == 0; };
   auto enqueue_eval = [&](int k) {
+    const bool prof = sampled(eval_index++);
+    hipEvent_t e0 = prof ? pev[2 * k] : nullptr, e1 = prof ? pev[2 * k + 1] : nullptr;
     if (dim == 1) {
-      if (o.profile) (void)hipEventRecord(pev[2 * k], c->s);
-      launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), threads, smem[0], P, S, (const int2*)dbm[0],
-                         c->twd, c->twf);
-      if (o.profile) (void)hipEventRecord(pev[2 * k + 1], c->s);
+      launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, (const int2*)dbm[0],
+                         c->twd, c->twf, e0, e1);
     } else {
-      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), threads, smem[0], P, S, (const int2*)dbm[0],
+      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, (const int2*)dbm[0],
                          c->twd, c->twf);
       if (dim == 3)
-        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), threads, smem[1], P, S, (const int2*)dbm[1],
+        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, S, (const int2*)dbm[1],
                            c->twd, c->twf);
-      if (o.profile) (void)hipEventRecord(pev[2 * k], c->s);
-      launch_solver_pass(c->s, R_FINAL, prec64, (int)bm[dim - 1].size(), threads, smem[dim - 1], P, S,
-                         (const int2*)dbm[dim - 1], c->twd, c->twf);
-      if (o.profile) (void)hipEventRecord(pev[2 * k + 1], c->s);
+      launch_solver_pass(c->s, R_FINAL, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
+                         (const int2*)dbm[dim - 1], c->twd, c->twf, e0, e1);
     }
-    launch_step(c->s, count, P, S, prec64);
+    if (!fuse) launch_step(c->s, count, P, S, prec64);
   };
   auto free_events = [&]() {
     for (auto& e : pev)
@@ -452,7 +482,8 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (o.use_graph) {
+  // (event records are not captured into graphs: profiling uses plain launches)
+  if (o.use_graph && !o.profile) {
     HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < o.chunk; ++k) enqueue_eval(k);
     HIPCHK(hipStreamEndCapture(c->s, &graph));
@@ -488,6 +519,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       // launches of this chunk during which some problem was still active
       const int64_t act = std::min<int64_t>(o.chunk, std::max<int64_t>(0, maxnfe - (evals - o.chunk)));
       for (int64_t k = 0; k < act; ++k) {
+        if (!sampled(evals - o.chunk + k)) continue;
         float e = 0.0f;
         if (hipEventElapsedTime(&e, pev[2 * k], pev[2 * k + 1]) == hipSuccess) {
           pass_ms += e;

@@ -8,16 +8,22 @@ namespace gpe {
 
 template <int N, int ROLE, typename T>
 __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A, int tile, cx<T>* lds,
-                                           const cx<T>* tw, double* red) {
+                                           const cx<T>* tw1024, double* red) {
   constexpr int E = Tile<N>::E;
+  constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   const int ax = role_axis(ROLE, P.dim);
-  const Tile<N> Tl(P, ax, ROLE == R_MID || ROLE == R_FINAL, tile);
+  const Tile<N> Tl(P, ax, HAS_T, tile);
+  load_twiddles<N>(lds, tw1024);
   const cx<T>* in = reinterpret_cast<const cx<T>*>(A.in);
-  cx<T> v[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = Tl.act ? in[Tl.g(e)] : cx<T>{0, 0};
-  spectral_apply<N, T>(P, ax, Tl, v, lds, tw);
   cx<T>* tacc = reinterpret_cast<cx<T>*>(P.t);
+  cx<T> u[E], tv[E], v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    u[e] = Tl.act ? in[Tl.g(e)] : cx<T>{0, 0};
+    if constexpr (HAS_T) tv[e] = Tl.act ? tacc[Tl.g(e)] : cx<T>{0, 0};
+    v[e] = u[e];
+  }
+  spectral_apply<N, T>(P, ax, Tl, v, lds);
   if constexpr (ROLE == R_FIRST) {
     if (Tl.act)
 #pragma unroll
@@ -25,48 +31,36 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
   } else if constexpr (ROLE == R_MID) {
     if (Tl.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int64_t g = Tl.g(e);
-        tacc[g] = tacc[g] + v[e];
-      }
+      for (int e = 0; e < E; ++e) tacc[Tl.g(e)] = tv[e] + v[e];
   } else {
     double acc[SA_COUNT] = {};
     cx<T>* out = reinterpret_cast<cx<T>*>(A.out);
-    __syncthreads();  // LDS free again: stage the spectral results per thread
-#pragma unroll
-    for (int e = 0; e < E; ++e) lds[Tl.mp.idx(Tl.lane, Tl.t + e * Tl.TL, N)] = v[e];
     if (Tl.act)
-#pragma unroll 1
+#pragma unroll
       for (int e = 0; e < E; ++e) {
         const int64_t g = Tl.g(e);
-        cx<double> kin = cvt<double>(lds[Tl.mp.idx(Tl.lane, Tl.t + e * Tl.TL, N)]);
-        if constexpr (ROLE == R_FINAL) kin = kin + cvt<double>(tacc[g]);
-        const cx<double> u = cvt<double>(in[g]);
-        const double vg = potential_at(P, g);
-        const double q = abs2(u);
+        cx<double> kin = cvt<double>(v[e]);
+        if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
+        const cx<double> uu = cvt<double>(u[e]);
+        const double vg = Tl.pot(P, e);
+        const double q = abs2(uu);
         if (A.kind == 0) {
-          const cx<double> h = kin + vg * u + (P.beta * q) * u;
+          const cx<double> h = kin + vg * uu + (P.beta * q) * uu;
           out[g] = cvt<T>(h);
-          acc[SA_KIN] += redot(u, kin);
+          acc[SA_KIN] += redot(uu, kin);
           acc[SA_POT] += vg * q;
           acc[SA_QUART] += q * q;
           acc[SA_NORM] += q;
-          const int64_t ix = g % P.n[0];
-          const double x = P.lo[0] + P.h[0] * (double)ix;
-          acc[SA_X2] += x * x * q;
-          if (P.dim > 1) {
-            const double y = P.lo[1] + P.h[1] * (double)((g / P.n[0]) % P.n[1]);
-            acc[SA_Y2] += y * y * q;
-          }
-          if (P.dim > 2) {
-            const double z = P.lo[2] + P.h[2] * (double)(g / P.stride[2]);
-            acc[SA_Z2] += z * z * q;
+          for (int a = 0; a < P.dim; ++a) {
+            const int ia = a == ax ? Tl.pos(e) : Tl.c[a];
+            const double xa = P.lo[a] + P.h[a] * (double)ia;
+            acc[SA_X2 + a] += xa * xa * q;
           }
           acc[SA_MAXD] = fmax(acc[SA_MAXD], q);
         } else {
           const cx<double> x0 = reinterpret_cast<const cx<double>*>(A.xk)[g];
-          const cx<double> hs = 2.0 * (kin + vg * u) +
-                                (4.0 * P.alpha) * (abs2(x0) * u + (2.0 * redot(x0, u)) * x0) + A.delta * u;
+          const cx<double> hs = 2.0 * (kin + vg * uu) +
+                                (4.0 * P.alpha) * (abs2(x0) * uu + (2.0 * redot(x0, uu)) * x0) + A.delta * uu;
           out[g] = cvt<T>(hs);
         }
       }

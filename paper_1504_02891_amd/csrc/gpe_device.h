@@ -131,19 +131,23 @@ __device__ __forceinline__ void dftR(cx<T>* u) {
 }
 
 // ---------------------------------------------------------------------------
-// Line FFT plan: N points handled by TL threads holding E = N/TL values each.
-// Thread t holds v[e] = line[t + e*TL] before and after a transform.
-// Radix-16 stages, then one stage of the remaining factor; the inverse runs
-// the stages in reverse order so that the forward output stays in registers.
+// Line FFT plan: N points handled by TL = N/E threads holding E = 8 values
+// each; thread t holds v[e] = line[t + e*TL] before and after a transform.
+// Radix-8 stages, then one stage of the remaining factor; the inverse runs
+// the stages in reverse order so that the forward output (natural frequency
+// order, register e = frequency t + e*TL) stays in registers across the
+// multiplier.  Twiddles come from a per-workgroup LDS table
+// tw[m] = exp(-2 pi i m / N), m < N.
 // ---------------------------------------------------------------------------
 template <int N> struct Plan;
-template <> struct Plan<16>   { static constexpr int E = 16, NS = 1; static constexpr int R[1] = {16}; };
-template <> struct Plan<32>   { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 2}; };
-template <> struct Plan<64>   { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 4}; };
-template <> struct Plan<128>  { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 8}; };
-template <> struct Plan<256>  { static constexpr int E = 16, NS = 2; static constexpr int R[2] = {16, 16}; };
-template <> struct Plan<512>  { static constexpr int E = 16, NS = 3; static constexpr int R[3] = {16, 16, 2}; };
-template <> struct Plan<1024> { static constexpr int E = 16, NS = 3; static constexpr int R[3] = {16, 16, 4}; };
+template <> struct Plan<16>   { static constexpr int E = 8, NS = 2; static constexpr int R[2] = {8, 2}; };
+template <> struct Plan<32>   { static constexpr int E = 8, NS = 2; static constexpr int R[2] = {8, 4}; };
+template <> struct Plan<64>   { static constexpr int E = 8, NS = 2; static constexpr int R[2] = {8, 8}; };
+template <> struct Plan<128>  { static constexpr int E = 8, NS = 3; static constexpr int R[3] = {8, 8, 2}; };
+template <> struct Plan<256>  { static constexpr int E = 8, NS = 3; static constexpr int R[3] = {8, 8, 4}; };
+template <> struct Plan<512>  { static constexpr int E = 8, NS = 3; static constexpr int R[3] = {8, 8, 8}; };
+template <> struct Plan<1024> { static constexpr int E = 8, NS = 4; static constexpr int R[4] = {8, 8, 8, 2}; };
+static_assert(Plan<256>::E == kE, "host tiling assumes kE elements per thread");
 
 // LDS addressing of a line element: `lane` is the line inside the tile,
 // `pos` the position on the line.  Contiguous tiles store lines one after
@@ -158,10 +162,14 @@ struct LdsMap {
     return lane * row + pos + (pos >> 4);
   }
 };
+// elements of LDS a tile of `lanes` lines of n points needs (data region)
+__host__ __device__ inline int lds_elems(int n, int lanes, bool strided) {
+  return strided ? n * (lanes + 1) : lanes * (n + n / 16);
+}
 
 template <int N, int R, bool INV, bool LAST, typename T>
 __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, int ns, int lane, const LdsMap& mp,
-                                               cx<T>* lds, const cx<T>* tw) {
+                                               cx<T>* lds, const cx<T>* twl) {
   constexpr int E = Plan<N>::E;
   constexpr int TL = N / E;
   constexpr int B = E / R;  // butterflies per thread
@@ -174,10 +182,10 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, int ns, int lane
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[i + r * B];
     if (ns > 1) {
-      const int step = kTwN / (ns * R);
+      const int step = N / (ns * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cx<T> w = tw[(r * k * step) & (kTwN - 1)];
+        const cx<T> w = twl[(r * k * step) & (N - 1)];
         u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
       }
     }
@@ -201,30 +209,31 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, int ns, int lane
   }
 }
 
-// Full line transform; every thread of the block must call it (barriers).
-// `fresh` = true when the LDS buffer was not read since the last barrier.
+template <int N, bool INV, int S, typename T>
+__device__ __forceinline__ void run_stages(cx<T>* v, int t, int ns, int lane, const LdsMap& mp, cx<T>* lds,
+                                           const cx<T>* twl) {
+  using P = Plan<N>;
+  if constexpr (S < P::NS) {
+    constexpr int R = INV ? P::R[P::NS - 1 - S] : P::R[S];
+    constexpr bool LAST = (S == P::NS - 1);
+    if constexpr (!LAST) __syncthreads();   // nobody still reads the LDS lines
+    stockham_stage<N, R, INV, LAST>(v, t, ns, lane, mp, lds, twl);
+    run_stages<N, INV, S + 1>(v, t, ns * R, lane, mp, lds, twl);
+  }
+}
+
+// Full line transform; every thread of the workgroup must call it (barriers).
 template <int N, bool INV, typename T>
 __device__ __forceinline__ void line_fft(cx<T>* v, int t, int lane, const LdsMap& mp, cx<T>* lds,
-                                         const cx<T>* tw) {
-  using P = Plan<N>;
-  if constexpr (P::NS == 1) {
-    stockham_stage<N, P::R[0], INV, true>(v, t, 1, lane, mp, lds, tw);
-  } else if constexpr (P::NS == 2) {
-    constexpr int R0 = INV ? P::R[1] : P::R[0];
-    constexpr int R1 = INV ? P::R[0] : P::R[1];
-    __syncthreads();
-    stockham_stage<N, R0, INV, false>(v, t, 1, lane, mp, lds, tw);
-    stockham_stage<N, R1, INV, true>(v, t, R0, lane, mp, lds, tw);
-  } else {
-    constexpr int R0 = INV ? P::R[2] : P::R[0];
-    constexpr int R1 = P::R[1];
-    constexpr int R2 = INV ? P::R[0] : P::R[2];
-    __syncthreads();
-    stockham_stage<N, R0, INV, false>(v, t, 1, lane, mp, lds, tw);
-    __syncthreads();
-    stockham_stage<N, R1, INV, false>(v, t, R0, lane, mp, lds, tw);
-    stockham_stage<N, R2, INV, true>(v, t, R0 * R1, lane, mp, lds, tw);
-  }
+                                         const cx<T>* twl) {
+  run_stages<N, INV, 0>(v, t, 1, lane, mp, lds, twl);
+}
+
+// Per-workgroup twiddle table exp(-2 pi i m / N) from the 1024-entry table.
+// Callers issue it before a barrier that precedes the first stage using it.
+template <int N, typename T>
+__device__ __forceinline__ void load_twiddles(cx<T>* twl, const cx<T>* tw1024) {
+  for (int m = threadIdx.x; m < N; m += blockDim.x) twl[m] = tw1024[m * (kTwN / N)];
 }
 
 // ---------------------------------------------------------------------------

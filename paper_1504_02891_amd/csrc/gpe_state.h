@@ -6,6 +6,7 @@ namespace gpe {
 
 constexpr int kMaxN = 1024;          // largest points per axis
 constexpr int kTwN = 1024;           // twiddle table length: exp(-2 pi i m / 1024)
+constexpr int kE = 8;                // line elements held per thread in the passes
 
 // Reduction slots of the first pass of an evaluation (sums and one max).
 enum Slot1 { S1_NY = 0, S1_NP2, S1_COUNT_SUM, S1_RMAX = S1_COUNT_SUM, S1_COUNT };
@@ -52,7 +53,7 @@ struct ProbDev {
   int32_t tiles[3];      // tiles (blocks) per pass along axis 0, 1, 2
   int32_t lanes[3];      // lines per tile in each pass
   int32_t has_v;         // 1: read v_arr, 0: separable v_axis tables
-  int32_t pad0;
+  int32_t fuse_step;     // 1: the final pass's last workgroup runs the scalar step
   double lo[3], h[3], len[3];
   double beta, omega, hvol, sqrt_hvol, alpha;
   const double* v_arr;   // explicit V (float64), or null
@@ -67,6 +68,7 @@ struct ProbDev {
   void* t;               // accumulator of the directional passes (complex double sized)
   double* part1;         // [tiles[0]][S1_COUNT]
   double* partF;         // [tiles[dim-1]][SF_COUNT]
+  int32_t* ticket;       // workgroups of the final pass done (reset by the last one)
   const void* user_in;   // apply / init input
   void* user_out;        // apply output
 };
@@ -94,6 +96,12 @@ struct SolverState {
   double eta1, eta2, gshrink, ggrow, delta_min, delta_max;
   int32_t k_init, k_sub, m_max, max_iter;
 };
+
+// LDS elements (complex) a tile of `lanes` lines of n points needs for its
+// line data (must match LdsMap in the device code).
+inline int lds_elems_host(int n, int lanes, bool strided) {
+  return strided ? n * (lanes + 1) : lanes * (n + n / 16);
+}
 
 // Arguments of the stand-alone apply passes.
 // kind 0: H(phi) phi in phi units; kind 1: Hessian-vector product in X units.

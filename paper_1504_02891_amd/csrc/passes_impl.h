@@ -2,13 +2,15 @@
 // ground-state solver.  One evaluation of a d-dimensional problem is d
 // launches: FIRST (x-lines, contiguous), MID (y-lines, 3D only), FINAL (last
 // axis, strided).  A 1D problem is one SOLO launch.  Every pass loads the
-// trial point, transforms each line, multiplies by the axis multiplier
-// (lambda^2/2 + rotation term, §2.3) and transforms back; the final pass adds
-// the other axes' results, V and the nonlinearity, and reduces the scalars
-// the step kernel needs.
+// trial point's inputs once into registers, transforms each line, multiplies
+// by the axis multiplier (lambda^2/2 + rotation term, §2.3) and transforms
+// back; the final pass adds the other axes' results, V and the nonlinearity
+// from the same registers, reduces the scalars of the evaluation, and its
+// last workgroup runs the solver's scalar step.
 #pragma once
 #include <type_traits>
 #include "gpe_device.h"
+#include "step_impl.h"
 
 namespace gpe {
 
@@ -16,65 +18,70 @@ __device__ __forceinline__ int role_axis(int role, int dim) {
   return role == R_FIRST || role == R_SOLO ? 0 : (role == R_MID ? 1 : dim - 1);
 }
 __device__ __forceinline__ int64_t pass_cols(const ProbDev& P, int ax) { return P.m / P.n[ax]; }
-__device__ __forceinline__ int64_t col_base(const ProbDev& P, int ax, int64_t col) {
-  if (ax == 0) return col * P.n[0];
-  if (ax == 1) {
-    const int64_t x = col % P.n[0], z = col / P.n[0];
-    return z * P.stride[2] + x;
+
+// Thread layout of a tile: `lanes` lines of N points, TL threads per line.
+// The grid coordinates of a line (all but the one along the pass axis) are
+// decoded once per tile with 32-bit arithmetic.
+template <int N>
+struct Tile {
+  static constexpr int E = Plan<N>::E, TL = N / E;
+  int lanes, lane, t, ax;
+  int c[3];          // coordinates of the line's first point
+  bool act;
+  int64_t base, st;
+  double vcol;       // potential of the fixed coordinates (separable V)
+  LdsMap mp;
+  __device__ __forceinline__ Tile(const ProbDev& P, int ax_, bool strided, int tile) {
+    ax = ax_;
+    lanes = blockDim.x / TL;
+    if (strided) { lane = threadIdx.x % lanes; t = threadIdx.x / lanes; }
+    else { lane = threadIdx.x / TL; t = threadIdx.x % TL; }
+    const int col = tile * lanes + lane;
+    act = col < (int)pass_cols(P, ax);
+    const int cc = act ? col : 0;
+    const int n0 = P.n[0], n1 = P.n[1];
+    if (ax == 0) { c[0] = 0; c[1] = cc % n1; c[2] = cc / n1; }
+    else if (ax == 1) { c[0] = cc % n0; c[1] = 0; c[2] = cc / n0; }
+    else { c[0] = cc % n0; c[1] = cc / n0; c[2] = 0; }
+    base = (int64_t)c[0] + (int64_t)c[1] * P.stride[1] + (int64_t)c[2] * P.stride[2];
+    st = P.stride[ax];
+    vcol = 0.0;
+    if (!P.has_v)
+      for (int a = 0; a < P.dim; ++a)
+        if (a != ax) vcol += P.v_axis[a * kMaxN + c[a]];
+    mp.lanes = lanes;
+    mp.strided = strided;
   }
-  return col;
-}
-// Omega * (coordinate entering the first-derivative multiplier of this axis)
-__device__ __forceinline__ double rot_coef(const ProbDev& P, int ax, int64_t col) {
-  if (P.dim < 2 || P.omega == 0.0) return 0.0;
-  if (ax == 0) return P.omega * (P.lo[1] + P.h[1] * (double)(col % P.n[1]));   // + Omega y
-  if (ax == 1) return -P.omega * (P.lo[0] + P.h[0] * (double)(col % P.n[0]));  // - Omega x
-  return 0.0;
-}
+  __device__ __forceinline__ int pos(int e) const { return t + e * TL; }
+  __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)(t + e * TL) * st; }
+  __device__ __forceinline__ double pot(const ProbDev& P, int e) const {
+    return P.has_v ? P.v_arr[g(e)] : vcol + P.v_axis[ax * kMaxN + pos(e)];
+  }
+  // Omega * (coordinate entering this axis' first-derivative multiplier)
+  __device__ __forceinline__ double rot(const ProbDev& P) const {
+    if (P.dim < 2 || P.omega == 0.0) return 0.0;
+    if (ax == 0) return P.omega * (P.lo[1] + P.h[1] * (double)c[1]);    // + Omega y
+    if (ax == 1) return -P.omega * (P.lo[0] + P.h[0] * (double)c[0]);   // - Omega x
+    return 0.0;
+  }
+};
+
 template <typename CT>
 __device__ __forceinline__ CT axis_mult(int k, int n, CT two_pi_over_len, CT rc, CT inv_n) {
   const int p = k < (n >> 1) ? k : k - n;
   const CT lam = two_pi_over_len * (CT)p;
   return ((CT)0.5 * lam * lam + rc * lam) * inv_n;
 }
-__device__ __forceinline__ double potential_at(const ProbDev& P, int64_t g) {
-  if (P.has_v) return P.v_arr[g];
-  const int64_t ix = g % P.n[0];
-  double v = P.v_axis[ix];
-  if (P.dim > 1) v += P.v_axis[kMaxN + (g / P.n[0]) % P.n[1]];
-  if (P.dim > 2) v += P.v_axis[2 * kMaxN + g / P.stride[2]];
-  return v;
-}
-
-// Thread layout of a tile: `lanes` lines of N points, TL threads per line.
-template <int N>
-struct Tile {
-  static constexpr int E = Plan<N>::E, TL = N / E;
-  int lanes, lane, t;
-  int64_t col;
-  bool act;
-  int64_t base, st;
-  LdsMap mp;
-  __device__ __forceinline__ Tile(const ProbDev& P, int ax, bool strided, int tile) {
-    lanes = blockDim.x / TL;
-    if (strided) { lane = threadIdx.x % lanes; t = threadIdx.x / lanes; }
-    else { lane = threadIdx.x / TL; t = threadIdx.x % TL; }
-    col = (int64_t)tile * lanes + lane;
-    act = col < pass_cols(P, ax);
-    base = act ? col_base(P, ax, col) : 0;
-    st = P.stride[ax];
-    mp.lanes = lanes;
-    mp.strided = strided;
-  }
-  __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)(t + e * TL) * st; }
-};
 
 // Forward transform, multiplier, inverse transform of the tile's lines.
+// `lds` holds the twiddle table (N entries) followed by the line data.
 template <int N, typename CT>
 __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
-                                               cx<CT>* lds, const cx<CT>* tw) {
-  line_fft<N, false>(v, T.t, T.lane, T.mp, lds, tw);
-  const CT rc = (CT)rot_coef(P, ax, T.col);
+                                               cx<CT>* lds) {
+  const cx<CT>* twl = lds;
+  cx<CT>* data = lds + N;
+  line_fft<N, false>(v, T.t, T.lane, T.mp, data, twl);
+  const CT rc = (CT)T.rot(P);
   const CT tpl = (CT)(6.283185307179586477 / P.len[ax]);
   const CT inv_n = (CT)1 / (CT)N;
 #pragma unroll
@@ -82,31 +89,58 @@ __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const T
     const CT mlt = axis_mult<CT>(T.t + e * Tile<N>::TL, N, tpl, rc, inv_n);
     v[e] = mlt * v[e];
   }
-  line_fft<N, true>(v, T.t, T.lane, T.mp, lds, tw);
+  line_fft<N, true>(v, T.t, T.lane, T.mp, data, twl);
 }
 
-// Deterministic sum (or max) of part[i*stride + slot] over i < count, done by
-// the block's first wavefront (lane l takes i = l, l+64, ...; then a
-// butterfly).  The final pass and the step kernel both use it, so the
-// renormalisation factor they derive from the first-pass sums agrees bitwise.
+// Deterministic reduction of part[i*stride + s], i < count, for slots
+// s < NSLOT (slot s is a max when bit s of `maxmask` is set, else a sum),
+// done by the workgroup's first wavefront: lane l takes i = l, l+64, ... in
+// order, then a butterfly.  All loads of a lane are independent (one memory
+// round trip).  The final pass and the scalar step both use this order, so
+// values derived from the same partials agree bitwise.  Every thread gets
+// the result.
+template <int NSLOT>
+__device__ __forceinline__ void reduce_partials(const double* part, int count, int stride, unsigned maxmask,
+                                                double* out, double* red) {
+  if (threadIdx.x < 64) {
+    double acc[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;
+    for (int i = threadIdx.x; i < count; i += 64) {
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) {
+        const double v = part[(int64_t)i * stride + s];
+        acc[s] = ((maxmask >> s) & 1u) ? fmax(acc[s], v) : acc[s] + v;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) acc[s] = ((maxmask >> s) & 1u) ? wave_max(acc[s]) : wave_sum(acc[s]);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) red[s] = acc[s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) out[s] = red[s];
+  __syncthreads();
+}
+// one slot with the same arithmetic (slots are reduced independently, so
+// this equals slot `slot` of the multi-slot call bitwise)
 __device__ __forceinline__ double fixed_reduce(const double* part, int count, int stride, int slot,
                                                bool is_max, double* red) {
   if (threadIdx.x < 64) {
-    double s = 0.0;
+    double a = 0.0;
     for (int i = threadIdx.x; i < count; i += 64) {
       const double v = part[(int64_t)i * stride + slot];
-      s = is_max ? fmax(s, v) : s + v;
+      a = is_max ? fmax(a, v) : a + v;
     }
-    s = is_max ? wave_max(s) : wave_sum(s);
-    if (threadIdx.x == 0) red[0] = s;
+    a = is_max ? wave_max(a) : wave_sum(a);
+    if (threadIdx.x == 0) red[0] = a;
   }
   __syncthreads();
   const double r = red[0];
   __syncthreads();
   return r;
-}
-__device__ __forceinline__ double sum_part1(const ProbDev& P, int slot, double* red) {
-  return fixed_reduce(P.part1, P.tiles[0], S1_COUNT, slot, false, red);
 }
 __device__ __forceinline__ double renorm_c(const SolverState& S, double ny) {
   return (S.force_norm || fabs(ny - 1.0) > S.renorm_tol) ? 1.0 / sqrt(ny) : 1.0;
@@ -118,12 +152,10 @@ template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, int64_t
 template <typename T> __device__ __forceinline__ void stc(void* p, int64_t g, cx<T> v) {
   reinterpret_cast<cx<T>*>(p)[g] = v;
 }
-template <typename T> __device__ __forceinline__ cx<double> rnd(cx<double> a) {  // round through storage type
-  return cvt<double>(cvt<T>(a));
-}
 
 // ---------------------------------------------------------------------------
-// Per-mode load (trial point) and epilogue.
+// Per-mode inputs (kept in registers for the whole pass), trial point and
+// epilogue.
 // ---------------------------------------------------------------------------
 struct Acc1 { double ny = 0.0, np2 = 0.0, rmax = 0.0; };
 struct AccF { double s[SF_COUNT_SUM] = {}; double smax = 0.0; };
@@ -131,32 +163,30 @@ struct AccF { double s[SF_COUNT_SUM] = {}; double smax = 0.0; };
 // Algorithm 1 on F: Y = p X_b + q G_b.
 template <typename TF>
 struct FOps {
+  struct In { cx<TF> x, g; };
   const ProbDev& P; const SolverState& S;
   const void *xb, *gb; void *xo, *go;
   __device__ FOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
     xb = P.xf[S.cur]; gb = P.gf[S.cur]; xo = P.xf[S.cur ^ 1]; go = P.gf[S.cur ^ 1];
   }
-  __device__ __forceinline__ cx<double> trial(int64_t g) const {
-    const cx<double> x = cvt<double>(ld<TF>(xb, g)), gr = cvt<double>(ld<TF>(gb, g));
-    return S.p * x + S.q * gr;
+  __device__ __forceinline__ In load(int64_t g) const { return In{ld<TF>(xb, g), ld<TF>(gb, g)}; }
+  __device__ __forceinline__ cx<double> trial(const In& in) const {
+    return S.p * cvt<double>(in.x) + S.q * cvt<double>(in.g);
   }
-  __device__ __forceinline__ cx<double> load_first(int64_t g, Acc1& a) const {
-    const cx<double> x = cvt<double>(ld<TF>(xb, g)), gr = cvt<double>(ld<TF>(gb, g));
-    const cx<double> pb = S.n_b * gr - S.a_b * x;
-    a.np2 += abs2(pb);
-    a.rmax = fmax(a.rmax, sqrt(abs2(gr - (S.a_b / S.n_b) * x)));
-    const cx<double> y = S.p * x + S.q * gr;
+  __device__ __forceinline__ void metrics1(const In& in, cx<double> y, Acc1& a) const {
+    const cx<double> x = cvt<double>(in.x), gr = cvt<double>(in.g);
+    a.np2 += abs2(S.n_b * gr - S.a_b * x);
+    a.rmax = fmax(a.rmax, abs2(gr - (S.a_b / S.n_b) * x));
     a.ny += abs2(y);
-    return y;
   }
   // kin: kinetic(+rotation) part of H_lin applied to the unscaled trial
-  __device__ __forceinline__ void final_(int64_t g, cx<double> kin, double c, double n_hat, AccF& a) const {
-    const cx<double> x = cvt<double>(ld<TF>(xb, g)), gr = cvt<double>(ld<TF>(gb, g));
-    const cx<double> y0 = S.p * x + S.q * gr;
-    const cx<TF> ys = cvt<TF>(c * y0);
+  __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c,
+                                         double n_hat, AccF& a) const {
+    const cx<double> x = cvt<double>(in.x), gr = cvt<double>(in.g);
+    const cx<TF> ys = cvt<TF>(c * trial(in));
     const cx<double> y = cvt<double>(ys);
     const double q = abs2(y);
-    const cx<double> ay = 2.0 * (c * kin + potential_at(P, g) * y);
+    const cx<double> ay = 2.0 * (c * kin + vg * y);
     const cx<TF> gs = cvt<TF>(ay + (4.0 * P.alpha * q) * y);
     const cx<double> gy = cvt<double>(gs);
     stc<TF>(xo, g, ys);
@@ -182,6 +212,7 @@ struct FOps {
 // S_new = (p-1) X_k + p S_b + q (G_k + D_b).
 template <typename TW>
 struct WOps {
+  struct In { cx<double> xk, gk; cx<TW> s, d; };
   const ProbDev& P; const SolverState& S;
   const cx<double>*xk, *gk; const void *sb, *db; void *so, *dout;
   __device__ WOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
@@ -189,26 +220,22 @@ struct WOps {
     gk = reinterpret_cast<const cx<double>*>(P.gk);
     sb = P.s[S.cur]; db = P.d[S.cur]; so = P.s[S.cur ^ 1]; dout = P.d[S.cur ^ 1];
   }
-  __device__ __forceinline__ cx<double> trial(int64_t g) const {
-    const cx<double> s = cvt<double>(ld<TW>(sb, g)), d = cvt<double>(ld<TW>(db, g));
-    return S.pm1 * xk[g] + S.p * s + S.q * (gk[g] + d);
+  __device__ __forceinline__ In load(int64_t g) const { return In{xk[g], gk[g], ld<TW>(sb, g), ld<TW>(db, g)}; }
+  __device__ __forceinline__ cx<double> trial(const In& in) const {
+    return S.pm1 * in.xk + S.p * cvt<double>(in.s) + S.q * (in.gk + cvt<double>(in.d));
   }
-  __device__ __forceinline__ cx<double> load_first(int64_t g, Acc1& a) const {
-    const cx<double> x0 = xk[g], g0 = gk[g];
-    const cx<double> s = cvt<double>(ld<TW>(sb, g)), d = cvt<double>(ld<TW>(db, g));
-    const cx<double> gb = g0 + d, xb = x0 + s;
-    const cx<double> pb = (S.n_b * g0 - S.a_b * x0) + (S.n_b * d - S.a_b * s);
-    a.np2 += abs2(pb);
-    a.rmax = fmax(a.rmax, sqrt(abs2(gb - (S.a_b / S.n_b) * xb)));
-    const cx<double> sn = S.pm1 * x0 + S.p * s + S.q * gb;
-    a.ny += abs2(x0 + sn);
-    return sn;
+  __device__ __forceinline__ void metrics1(const In& in, cx<double> sn, Acc1& a) const {
+    const cx<double> s = cvt<double>(in.s), d = cvt<double>(in.d);
+    const cx<double> gb = in.gk + d, xb = in.xk + s;
+    a.np2 += abs2((S.n_b * in.gk - S.a_b * in.xk) + (S.n_b * d - S.a_b * s));
+    a.rmax = fmax(a.rmax, abs2(gb - (S.a_b / S.n_b) * xb));
+    a.ny += abs2(in.xk + sn);
   }
-  __device__ __forceinline__ void final_(int64_t g, cx<double> kin, double c, double n_hat, AccF& a) const {
-    const cx<double> x0 = xk[g], g0 = gk[g];
-    const cx<double> s = cvt<double>(ld<TW>(sb, g)), d = cvt<double>(ld<TW>(db, g));
-    const cx<double> sn = S.pm1 * x0 + S.p * s + S.q * (g0 + d);
-    const double vg = potential_at(P, g);
+  __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c,
+                                         double n_hat, AccF& a) const {
+    const cx<double> x0 = in.xk, g0 = in.gk;
+    const cx<double> s = cvt<double>(in.s), d = cvt<double>(in.d);
+    const cx<double> sn = trial(in);
     const double qk = abs2(x0);
     const double al4 = 4.0 * P.alpha;
     const cx<double> axk = g0 - (al4 * qk) * x0;                     // A X_k
@@ -243,26 +270,25 @@ struct WOps {
 // Float64 evaluation at a new outer iterate; writes X_k, G_k and clears S/D.
 template <typename TF, typename TW>
 struct OOps {
+  struct In { cx<double> y; };
   const ProbDev& P; const SolverState& S;
   cx<double>*xk, *gk;
   __device__ OOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
     xk = reinterpret_cast<cx<double>*>(P.xk);
     gk = reinterpret_cast<cx<double>*>(P.gk);
   }
-  __device__ __forceinline__ cx<double> trial(int64_t g) const {
-    if (S.src == SRC_XF) return cvt<double>(ld<TF>(P.xf[S.cur], g));
-    if (S.src == SRC_XK_PLUS_S) return xk[g] + cvt<double>(ld<TW>(P.s[S.cur], g));
-    return xk[g];
+  __device__ __forceinline__ In load(int64_t g) const {
+    if (S.src == SRC_XF) return In{cvt<double>(ld<TF>(P.xf[S.cur], g))};
+    if (S.src == SRC_XK_PLUS_S) return In{xk[g] + cvt<double>(ld<TW>(P.s[S.cur], g))};
+    return In{xk[g]};
   }
-  __device__ __forceinline__ cx<double> load_first(int64_t g, Acc1& a) const {
-    const cx<double> y = trial(g);
-    a.ny += abs2(y);
-    return y;
-  }
-  __device__ __forceinline__ void final_(int64_t g, cx<double> kin, double c, double, AccF& a) const {
-    const cx<double> y = c * trial(g);
+  __device__ __forceinline__ cx<double> trial(const In& in) const { return in.y; }
+  __device__ __forceinline__ void metrics1(const In&, cx<double> y, Acc1& a) const { a.ny += abs2(y); }
+  __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c, double,
+                                         AccF& a) const {
+    const cx<double> y = c * in.y;
     const double q = abs2(y);
-    const cx<double> ay = 2.0 * (c * kin + potential_at(P, g) * y);
+    const cx<double> ay = 2.0 * (c * kin + vg * y);
     const cx<double> gy = ay + (4.0 * P.alpha * q) * y;
     xk[g] = y;
     gk[g] = gy;
@@ -279,46 +305,53 @@ struct OOps {
 // One tile of one pass for a given mode.
 // ---------------------------------------------------------------------------
 template <int N, int ROLE, typename CT, class Ops>
-__device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState& S, int tile,
-                                            const Ops& ops, cx<CT>* lds, const cx<CT>* tw, double* red) {
+__device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState& S, int tile, const Ops& ops,
+                                            cx<CT>* lds, const cx<CT>* tw1024, double* red) {
   constexpr int E = Tile<N>::E;
+  constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   const int ax = role_axis(ROLE, P.dim);
-  const Tile<N> T(P, ax, ROLE == R_MID || ROLE == R_FINAL, tile);
+  const Tile<N> T(P, ax, HAS_T, tile);
+  load_twiddles<N>(lds, tw1024);
+  cx<CT>* tacc = reinterpret_cast<cx<CT>*>(P.t);
+  // every input of the thread's elements in one batch of independent loads
+  typename Ops::In in[E];
+  cx<CT> tv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (T.act) {
+      in[e] = ops.load(T.g(e));
+      if constexpr (HAS_T) tv[e] = tacc[T.g(e)];
+    }
+  }
   cx<CT> v[E];
   Acc1 a1;
-  // The trial point is formed element by element (a rolled loop keeps few
-  // loads in flight per thread) and staged through the thread's own LDS
-  // slots, then taken into registers for the transform.
-#pragma unroll 1
-  for (int e = 0; e < E; ++e) {
-    cx<CT> val{0, 0};
-    if (T.act) {
-      if constexpr (ROLE == R_FIRST || ROLE == R_SOLO) val = cvt<CT>(ops.load_first(T.g(e), a1));
-      else val = cvt<CT>(ops.trial(T.g(e)));
-    }
-    lds[T.mp.idx(T.lane, T.t + e * T.TL, N)] = val;
-  }
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = lds[T.mp.idx(T.lane, T.t + e * T.TL, N)];
+  for (int e = 0; e < E; ++e) {
+    cx<double> y{0.0, 0.0};
+    if (T.act) {
+      y = ops.trial(in[e]);
+      if constexpr (ROLE == R_FIRST || ROLE == R_SOLO) ops.metrics1(in[e], y, a1);
+    }
+    v[e] = cvt<CT>(y);
+  }
   double c = 1.0, n_hat = 1.0;
   if constexpr (ROLE == R_SOLO) {
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
     block_reduce<2, 1>(acc, red);
-    __shared__ double bc[3];
+    __shared__ double bc;
     if (threadIdx.x == 0) {
-      bc[0] = acc[0]; bc[1] = acc[1]; bc[2] = acc[2];
+      bc = acc[0];
       P.part1[S1_NY] = acc[0]; P.part1[S1_NP2] = acc[1]; P.part1[S1_RMAX] = acc[2];
     }
     __syncthreads();
-    c = renorm_c(S, bc[0]);
-    n_hat = c * c * bc[0];
+    c = renorm_c(S, bc);
+    n_hat = c * c * bc;
   } else if constexpr (ROLE == R_FINAL) {
-    const double ny = sum_part1(P, S1_NY, red);
+    const double ny = fixed_reduce(P.part1, P.tiles[0], S1_COUNT, S1_NY, false, red);
     c = renorm_c(S, ny);
     n_hat = c * c * ny;
   }
-  spectral_apply<N, CT>(P, ax, T, v, lds, tw);
-  cx<CT>* tacc = reinterpret_cast<cx<CT>*>(P.t);
+  spectral_apply<N, CT>(P, ax, T, v, lds);
   if constexpr (ROLE == R_FIRST) {
     if (T.act)
 #pragma unroll
@@ -332,22 +365,15 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   } else if constexpr (ROLE == R_MID) {
     if (T.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int64_t g = T.g(e);
-        tacc[g] = tacc[g] + v[e];
-      }
+      for (int e = 0; e < E; ++e) tacc[T.g(e)] = tv[e] + v[e];
   } else {
     AccF af;
-    __syncthreads();  // every thread has finished reading LDS in the inverse transform
-#pragma unroll
-    for (int e = 0; e < E; ++e) lds[T.mp.idx(T.lane, T.t + e * T.TL, N)] = v[e];
     if (T.act)
-#pragma unroll 1
+#pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int64_t g = T.g(e);
-        cx<double> kin = cvt<double>(lds[T.mp.idx(T.lane, T.t + e * T.TL, N)]);
-        if constexpr (ROLE == R_FINAL) kin = kin + cvt<double>(tacc[g]);
-        ops.final_(g, kin, c, n_hat, af);
+        cx<double> kin = cvt<double>(v[e]);
+        if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
+        ops.final_(in[e], T.g(e), T.pot(P, e), kin, c, n_hat, af);
       }
     double acc[SF_COUNT];
 #pragma unroll
@@ -362,21 +388,43 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   }
 }
 
+// The last workgroup to finish a problem's final pass (ticket counter) runs
+// the scalar step of the solver on the reduced partial sums.
+__device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState& S, int ntiles, int prec64,
+                                             double* red) {
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    int last = 1;
+    if (ntiles > 1) {
+      __threadfence();                       // publish this workgroup's partials
+      last = atomicAdd(P.ticket, 1) == ntiles - 1;
+      if (last) {
+        __threadfence();                     // see every other workgroup's partials
+        atomicExch(P.ticket, 0);
+      }
+    }
+    is_last = last;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  double r1[S1_COUNT], rf[SF_COUNT];
+  reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1, red);
+  reduce_partials<SF_COUNT>(P.partF, ntiles, SF_COUNT, 1u << SF_SMAX, rf, red);
+  if (threadIdx.x == 0) step_logic(P, S, r1, rf, prec64);
+}
+
 // Dispatch on the problem's mode.  PREC64: every array float64.
 template <int N, int ROLE, bool PREC64>
-__device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverState& S, int tile,
-                                                char* smem, const cx<double>* twd, const cx<float>* twf,
-                                                double* red) {
-  using TS = typename std::conditional<PREC64, double, float>::type;   // F/W storage
-  using CT = TS;                                                         // F/W transforms
+__device__ __forceinline__ void solver_dispatch(const ProbDev& P, SolverState& S, int tile, char* smem,
+                                                const cx<double>* twd, const cx<float>* twf, double* red) {
+  using TS = typename std::conditional<PREC64, double, float>::type;   // F/W storage and transforms
+  const cx<TS>* tws = PREC64 ? reinterpret_cast<const cx<TS>*>(twd) : reinterpret_cast<const cx<TS>*>(twf);
   if (S.mode == M_F) {
     FOps<TS> ops(P, S);
-    solver_tile<N, ROLE, CT>(P, S, tile, ops, reinterpret_cast<cx<CT>*>(smem),
-                             PREC64 ? reinterpret_cast<const cx<CT>*>(twd) : reinterpret_cast<const cx<CT>*>(twf), red);
+    solver_tile<N, ROLE, TS>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_W) {
     WOps<TS> ops(P, S);
-    solver_tile<N, ROLE, CT>(P, S, tile, ops, reinterpret_cast<cx<CT>*>(smem),
-                             PREC64 ? reinterpret_cast<const cx<CT>*>(twd) : reinterpret_cast<const cx<CT>*>(twf), red);
+    solver_tile<N, ROLE, TS>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_OUTER) {
     OOps<TS, TS> ops(P, S);
     solver_tile<N, ROLE, double>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd, red);
@@ -385,7 +433,7 @@ __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverSt
 
 template <int ROLE, bool PREC64>
 __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__ probs,
-                                                     const SolverState* __restrict__ states,
+                                                     SolverState* __restrict__ states,
                                                      const int2* __restrict__ bmap,
                                                      const cx<double>* __restrict__ twd,
                                                      const cx<float>* __restrict__ twf) {
@@ -393,7 +441,7 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   __shared__ double red[SF_COUNT * 16];
   const int2 bm = bmap[blockIdx.x];
   const ProbDev& P = probs[bm.x];
-  const SolverState& S = states[bm.x];
+  SolverState& S = states[bm.x];
   if (S.mode == M_IDLE) return;
   const int n = P.n[role_axis(ROLE, P.dim)];
   switch (n) {
@@ -406,6 +454,8 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
     case 1024: solver_dispatch<1024, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
     default: break;
   }
+  if constexpr (ROLE == R_FINAL || ROLE == R_SOLO)
+    if (P.fuse_step) step_if_last(P, S, ROLE == R_SOLO ? 1 : P.tiles[P.dim - 1], PREC64 ? 1 : 0, red);
 }
 
 }  // namespace gpe

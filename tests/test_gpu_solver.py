@@ -47,8 +47,8 @@ def _compare(p, phi_gpu, x_or, tol, e_rtol, phi_tol):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("beta", [400.0, 0.0])
-def test_config1_alg2(dev, prec, beta):
-    p, phi0 = W.config1(beta=beta)
+def test_harmonic_1d_alg2(dev, prec, beta):
+    p, phi0 = W.harmonic_1d(beta=beta)
     up = UnifiedProblem(p)
     ref = regularized_newton(up, up.to_x(phi0), Options(tol=1e-8))
     phi, res = _gpu_solve(dev, p, phi0, tol=1e-8, precision=prec)
@@ -58,16 +58,16 @@ def test_config1_alg2(dev, prec, beta):
     assert abs(og["energy"] - res["energy"]) < 1e-12 * og["energy"]
     if beta == 0.0:
         assert abs(res["energy"] - 0.5) < 1e-12
-    # real ground state up to the global phase (a zero mode of the energy that
-    # FP32 rounding in the mixed path can rotate)
+    # real ground state up to the global phase (a zero mode of the energy);
+    # the mixed path keeps its Newton corrections in FP32 (6e-8 relative)
     k = int(np.argmax(np.abs(phi)))
     real = phi * np.conj(phi[k]) / abs(phi[k])
-    assert float(np.max(np.abs(real.imag))) < 1e-9
+    assert float(np.max(np.abs(real.imag))) < (1e-9 if prec == "fp64" else 1e-6)
     assert abs(res["norm_err"]) < 1e-13
 
 
-def test_config1_alg1_fp64(dev):
-    p, phi0 = W.config1(beta=400.0)
+def test_harmonic_1d_alg1_fp64(dev):
+    p, phi0 = W.harmonic_1d(beta=400.0)
     up = UnifiedProblem(p)
     ref = feasible_only(up, up.to_x(phi0), Options(tol=1e-8))
     phi, res = _gpu_solve(dev, p, phi0, tol=1e-8, algorithm="alg1")
@@ -132,7 +132,7 @@ def test_cascadic_two_levels(dev):
 
 def test_error_paths(dev):
     from paper_1504_02891_amd.api import GpeError
-    p, phi0 = W.config1(beta=10.0)
+    p, phi0 = W.harmonic_1d(beta=10.0)
     z = torch.zeros(512, dtype=torch.complex128, device="cuda")
     with pytest.raises(GpeError) as e:
         dev.solve(p, z)

@@ -78,8 +78,8 @@ def test_alg1_sine_reproduces_printed_case2_lattice():
     _check_golden_1d("sine", 256, "sec4_1_case2.txt", lattice=True)
 
 
-def test_alg2_config1_matches_printed_and_alg1():
-    p, phi0 = W.config1(beta=400.0)
+def test_alg2_harmonic_1d_matches_printed_and_alg1():
+    p, phi0 = W.harmonic_1d(beta=400.0)
     up = UnifiedProblem(p)
     r2 = regularized_newton(up, up.to_x(phi0), Options(tol=1e-8))
     r1 = feasible_only(up, up.to_x(phi0), Options(tol=1e-8))
@@ -98,7 +98,7 @@ def test_alg2_config1_matches_printed_and_alg1():
 
 
 def test_beta0_gives_exact_harmonic_energy():
-    p, phi0 = W.config1(beta=0.0)
+    p, phi0 = W.harmonic_1d(beta=0.0)
     up = UnifiedProblem(p)
     res = regularized_newton(up, up.to_x(phi0), Options(tol=1e-8))
     out = up.outputs(res.x)
@@ -111,7 +111,7 @@ def test_virial_identity_at_convergence():
     # For phi -> lambda^{d/2} phi(lambda x) stationarity:
     # 2 E_kin - <x . grad V> + d E_int = 0, with <x.grad V> = 2 E_pot for a
     # harmonic trap.  E_kin excludes rotation (the L_z term is scale invariant).
-    for p, phi0, tol in ((W.config1()[0], W.config1()[1], 1e-9),):
+    for p, phi0, tol in ((W.harmonic_1d()[0], W.harmonic_1d()[1], 1e-9),):
         up = UnifiedProblem(p)
         res = regularized_newton(up, up.to_x(phi0), Options(tol=tol))
         x = res.x

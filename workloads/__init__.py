@@ -131,28 +131,28 @@ def rotating_initial(p: Problem, omega: float, seed: int, amp: float = 1e-3):
 
 
 # ---------------------------------------------------------------------------
-# The five benchmark configurations (1D harmonic; 2D rotating; 3D lattice;
-# batched 2D sweep; cascadic batch).  Each returns (problems, phi0s, meta).
+# Workloads: 1D harmonic trap; 2D rotating condensate; 3D optical lattice;
+# a batched sweep of rotating problems; a cascadic batch.
 # ---------------------------------------------------------------------------
 
-def config1(beta: float = 400.0, n: int = 512):
+def harmonic_1d(beta: float = 400.0, n: int = 512):
     p = Problem(dim=1, n=(n,), lo=(-16.0,), hi=(16.0,), beta=beta)
     return p, gaussian_times_noise(p, 0.05, seed=1)
 
 
-def config2(n: int = 256, beta: float = 1000.0, omega: float = 0.9, seed: int = 2):
+def rotating_2d(n: int = 256, beta: float = 1000.0, omega: float = 0.9, seed: int = 2):
     p = Problem(dim=2, n=(n, n), lo=(-12.0, -12.0), hi=(12.0, 12.0),
                 beta=beta, omega=omega)
     return p, rotating_initial(p, omega, seed)
 
 
-def config3(n: int = 128, beta: float = 1600.0, amp: float = 100.0, box: float = 16.0):
+def lattice_3d(n: int = 128, beta: float = 1600.0, amp: float = 100.0, box: float = 16.0):
     p = Problem(dim=3, n=(n, n, n), lo=(-box,) * 3, hi=(box,) * 3, beta=beta,
                 lattice_amp=amp)
     return p, gaussian_times_noise(p, 0.01, seed=3)
 
 
-def config4_params(count: int = 64):
+def rotating_sweep_params(count: int = 64):
     """(beta_i, omega_i, n_i) for the batched sweep, seed 4."""
     rng = np.random.default_rng(4)
     betas = rng.uniform(100.0, 2000.0, size=count)
@@ -161,8 +161,8 @@ def config4_params(count: int = 64):
     return betas, omegas, grids
 
 
-def config4(count: int = 64, grid_override=None):
-    betas, omegas, grids = config4_params(count)
+def rotating_sweep_2d(count: int = 64, grid_override=None):
+    betas, omegas, grids = rotating_sweep_params(count)
     probs, phis = [], []
     for i in range(count):
         n = grids[i] if grid_override is None else grid_override
@@ -173,7 +173,7 @@ def config4(count: int = 64, grid_override=None):
     return probs, phis
 
 
-def config5(levels=(64, 128, 256, 512), count: int = 16, beta: float = 5000.0):
+def cascade_2d(levels=(64, 128, 256, 512), count: int = 16, beta: float = 5000.0):
     omegas = [0.80 + 0.01 * i for i in range(count)]
     probs, phis = [], []
     for i, w in enumerate(omegas):
