@@ -52,6 +52,13 @@ extern "C" {
 #define GPE_ALG1             1   /* Algorithm 1 alone (§3.1) */
 #define GPE_ALG2             2   /* Algorithm 2: K_init steps of Algorithm 1, then regularized Newton (§3.2) */
 
+/* Placement of the scalar step (line search / trust-region update) that
+   follows each evaluation; results do not depend on it. */
+#define GPE_STEP_AUTO       -1   /* LAST_GROUP when the final pass has at most 128 workgroups
+                                    per problem (always in 1D), else KERNEL */
+#define GPE_STEP_LAST_GROUP  0   /* last workgroup of the final pass (a device-scope fence per workgroup) */
+#define GPE_STEP_KERNEL      1   /* a launch of its own after the final pass */
+
 /* ---- problem ------------------------------------------------------------ */
 typedef struct gpe_problem {
     int32_t dim;          /* 1, 2 or 3 */
@@ -87,10 +94,8 @@ typedef struct gpe_options {
                              (plain launches instead of a graph); 0: off */
     int32_t reserved0;
     int32_t threads[3];   /* workgroup size of the x, y, z passes (0 = built-in choice);
-                             must be a multiple of n/8 and at most 256 */
-    int32_t separate_step;/* scalar step: 1 its own launch, 0 in the last workgroup of the
-                             final pass (a device-scope fence per workgroup), -1 automatic
-                             (fused only when the final pass is one workgroup per problem) */
+                             a multiple of 64 and of n/8, at most 256 */
+    int32_t step_at;      /* where the scalar step of the solver runs (GPE_STEP_*) */
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */

@@ -23,6 +23,9 @@ GPE_PREC_FP64 = 0
 GPE_PREC_MIXED = 1
 GPE_ALG1 = 1
 GPE_ALG2 = 2
+GPE_STEP_AUTO = -1
+GPE_STEP_LAST_GROUP = 0
+GPE_STEP_KERNEL = 1
 
 EXPORTS = ("gpe_ctx_create", "gpe_ctx_destroy", "gpe_options_default", "gpe_strerror",
            "gpe_last_error", "gpe_apply_h", "gpe_hess_vec", "gpe_retract", "gpe_solve",
@@ -46,7 +49,7 @@ class Options(C.Structure):
                 ("gamma_grow", C.c_double),
                 ("delta0", C.c_double), ("delta_min", C.c_double), ("delta_max", C.c_double),
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("reserved0", C.c_int32), ("threads", C.c_int32 * 3), ("separate_step", C.c_int32)]
+                ("reserved0", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32)]
 
 
 class Result(C.Structure):

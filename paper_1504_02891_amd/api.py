@@ -77,6 +77,10 @@ def options(**kw):
     alg = kw.pop("algorithm", None)
     if alg is not None:
         o.algorithm = {"alg1": N.GPE_ALG1, "alg2": N.GPE_ALG2}.get(alg, alg)
+    step = kw.pop("step_at", None)
+    if step is not None:
+        o.step_at = {"auto": N.GPE_STEP_AUTO, "last_group": N.GPE_STEP_LAST_GROUP,
+                     "kernel": N.GPE_STEP_KERNEL}.get(step, step)
     thr = kw.pop("threads", None)
     if thr is not None:
         for i, t in enumerate(list(thr)[:3]):

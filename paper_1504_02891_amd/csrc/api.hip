@@ -228,7 +228,7 @@ void set_default(gpe_options* o) {
   o->profile = 0;
   o->reserved0 = 0;
   o->threads[0] = o->threads[1] = o->threads[2] = 0;
-  o->separate_step = -1;
+  o->step_at = GPE_STEP_AUTO;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,6 +321,7 @@ int check_options(const gpe_options* o) {
   if (!(o->sigma > 0.0 && o->sigma < 1.0) || !(o->eta >= 0.0 && o->eta < 1.0) || !(o->tau0 > 0.0))
     return GPE_EINVAL;
   if (o->chunk < 1 || o->chunk > 4096) return GPE_EINVAL;
+  if (o->step_at < GPE_STEP_AUTO || o->step_at > GPE_STEP_KERNEL) return GPE_EINVAL;
   return GPE_OK;
 }
 
@@ -352,7 +353,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   size_t smem[3] = {0, 0, 0};
   for (int ax = 0; ax < 3; ++ax) {
     const int th = o.threads[ax];
-    if (th != 0 && (th < 1 || th > 256)) return GPE_EINVAL;
+    if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
     for (int i = 0; i < count && th != 0 && ax < dim; ++i)
       if (th % (pd[i].n[ax] / kE) != 0) return GPE_EINVAL;
   }
@@ -371,12 +372,18 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     for (int i = 1; i < count; ++i)
       if (geo[(size_t)i * 3 + ax].threads != thr[ax]) return GPE_EUNSUPPORTED;  // one workgroup size per pass
   }
-  bool fuse = o.separate_step == 0;
-  if (o.separate_step < 0) {
-    fuse = true;
-    for (int i = 0; i < count; ++i) fuse = fuse && pd[i].tiles[dim - 1] == 1;
+  // placement of the scalar step: in the last workgroup of the final pass
+  // while that pass is small (a 1D problem is one workgroup, no fence needed),
+  // else a launch of its own (a device-scope fence per workgroup costs more
+  // than a launch once there are many workgroups)
+  int step_at = o.step_at;
+  if (step_at < 0) {
+    int maxt = 0;
+    for (int i = 0; i < count; ++i) maxt = std::max(maxt, pd[i].tiles[dim - 1]);
+    step_at = (dim == 1 || maxt <= 128) ? STEP_LAST_GROUP : STEP_KERNEL;
   }
-  for (int i = 0; i < count; ++i) pd[i].fuse_step = fuse ? 1 : 0;
+  for (int i = 0; i < count; ++i) pd[i].step_at = step_at;
+  const int chunk = o.chunk;
   // arena layout
   std::vector<ProbLayout> lay(count);
   size_t off = 0;
@@ -454,27 +461,29 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   // profile: an event pair around the last-axis pass of every evaluation
   std::vector<hipEvent_t> pev;
   if (o.profile) {
-    pev.resize(2 * (size_t)o.chunk, nullptr);
+    pev.resize(2 * (size_t)chunk, nullptr);
     for (auto& e : pev) HIPCHK(hipEventCreate(&e));
   }
   int64_t eval_index = 0;   // evaluations enqueued so far (profile sampling)
   auto sampled = [&](int64_t e) { return o.profile > 0 && e % o.profile == 0; };
+  // block maps are only needed for batches (workgroup b is tile b of a single problem)
+  auto bmap = [&](int ax) { return count == 1 ? nullptr : (const int2*)dbm[ax]; };
   auto enqueue_eval = [&](int k) {
     const bool prof = sampled(eval_index++);
     hipEvent_t e0 = prof ? pev[2 * k] : nullptr, e1 = prof ? pev[2 * k + 1] : nullptr;
     if (dim == 1) {
-      launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, (const int2*)dbm[0],
-                         c->twd, c->twf, e0, e1);
+      launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
+                         c->twf, e0, e1);
     } else {
-      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, (const int2*)dbm[0],
-                         c->twd, c->twf);
+      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
+                         c->twf);
       if (dim == 3)
-        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, S, (const int2*)dbm[1],
-                           c->twd, c->twf);
+        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, S, bmap(1), c->twd,
+                           c->twf);
       launch_solver_pass(c->s, R_FINAL, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
-                         (const int2*)dbm[dim - 1], c->twd, c->twf, e0, e1);
+                         bmap(dim - 1), c->twd, c->twf, e0, e1);
     }
-    if (!fuse) launch_step(c->s, count, P, S, prec64);
+    if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S, prec64);
   };
   auto free_events = [&]() {
     for (auto& e : pev)
@@ -485,7 +494,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   // (event records are not captured into graphs: profiling uses plain launches)
   if (o.use_graph && !o.profile) {
     HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < o.chunk; ++k) enqueue_eval(k);
+    for (int k = 0; k < chunk; ++k) enqueue_eval(k);
     HIPCHK(hipStreamEndCapture(c->s, &graph));
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
@@ -500,9 +509,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     if (exec) {
       if (hipGraphLaunch(exec, c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
     } else {
-      for (int k = 0; k < o.chunk; ++k) enqueue_eval(k);
+      for (int k = 0; k < chunk; ++k) enqueue_eval(k);
     }
-    evals += o.chunk;
+    evals += chunk;
     if (hipMemcpyAsync(pin, dstate, sizeof(SolverState) * count, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
         hipStreamSynchronize(c->s) != hipSuccess) {
       rc = GPE_EDEVICE;
@@ -517,9 +526,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
     if (o.profile) {
       // launches of this chunk during which some problem was still active
-      const int64_t act = std::min<int64_t>(o.chunk, std::max<int64_t>(0, maxnfe - (evals - o.chunk)));
+      const int64_t act = std::min<int64_t>(chunk, std::max<int64_t>(0, maxnfe - (evals - chunk)));
       for (int64_t k = 0; k < act; ++k) {
-        if (!sampled(evals - o.chunk + k)) continue;
+        if (!sampled(evals - chunk + k)) continue;
         float e = 0.0f;
         if (hipEventElapsedTime(&e, pev[2 * k], pev[2 * k + 1]) == hipSuccess) {
           pass_ms += e;

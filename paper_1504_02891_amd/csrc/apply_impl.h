@@ -12,29 +12,34 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
   constexpr int E = Tile<N>::E;
   constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   const int ax = role_axis(ROLE, P.dim);
+  constexpr bool EPI = (ROLE == R_FINAL || ROLE == R_SOLO);
   const Tile<N> Tl(P, ax, HAS_T, tile);
-  load_twiddles<N>(lds, tw1024);
-  const cx<T>* in = reinterpret_cast<const cx<T>*>(A.in);
-  cx<T>* tacc = reinterpret_cast<cx<T>*>(P.t);
+  TwiddleFetch<N, T> twf;
+  twf.fetch(tw1024);
+  // one batch of loads: input, accumulator, potential, X_k (Hessian-vector)
   cx<T> u[E], tv[E], v[E];
+  cx<double> xk[E];
+  double vp[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    u[e] = Tl.act ? in[Tl.g(e)] : cx<T>{0, 0};
-    if constexpr (HAS_T) tv[e] = Tl.act ? tacc[Tl.g(e)] : cx<T>{0, 0};
+    u[e] = ld<T>(A.in, Tl.g(e));
+    if constexpr (HAS_T) tv[e] = ld<T>(P.t, Tl.g(e));
+    if constexpr (EPI) xk[e] = A.kind == 1 ? ld<double>(A.xk, Tl.g(e)) : cx<double>{0.0, 0.0};
     v[e] = u[e];
   }
+  if constexpr (EPI) Tl.pot_load(P, vp);
+  twf.store(lds);
   spectral_apply<N, T>(P, ax, Tl, v, lds);
   if constexpr (ROLE == R_FIRST) {
     if (Tl.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) tacc[Tl.g(e)] = v[e];
+      for (int e = 0; e < E; ++e) stc<T>(P.t, Tl.g(e), v[e]);
   } else if constexpr (ROLE == R_MID) {
     if (Tl.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) tacc[Tl.g(e)] = tv[e] + v[e];
+      for (int e = 0; e < E; ++e) stc<T>(P.t, Tl.g(e), tv[e] + v[e]);
   } else {
     double acc[SA_COUNT] = {};
-    cx<T>* out = reinterpret_cast<cx<T>*>(A.out);
     if (Tl.act)
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -42,33 +47,36 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
         cx<double> kin = cvt<double>(v[e]);
         if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
         const cx<double> uu = cvt<double>(u[e]);
-        const double vg = Tl.pot(P, e);
+        const double vg = Tl.pot_value(P, vp[e]);
         const double q = abs2(uu);
         if (A.kind == 0) {
           const cx<double> h = kin + vg * uu + (P.beta * q) * uu;
-          out[g] = cvt<T>(h);
+          stc<T>(A.out, g, cvt<T>(h));
           acc[SA_KIN] += redot(uu, kin);
           acc[SA_POT] += vg * q;
           acc[SA_QUART] += q * q;
           acc[SA_NORM] += q;
-          for (int a = 0; a < P.dim; ++a) {
-            const int ia = a == ax ? Tl.pos(e) : Tl.c[a];
-            const double xa = P.lo[a] + P.h[a] * (double)ia;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            if (a >= P.dim) break;
+            const int ca = a == 0 ? Tl.c0 : (a == 1 ? Tl.c1 : Tl.c2);
+            const int ia = a == ax ? Tl.pos(e) : ca;
+            const double xa = P.lo[a] + P.h[a] * (double)ia;   // a is a compile-time index here
             acc[SA_X2 + a] += xa * xa * q;
           }
           acc[SA_MAXD] = fmax(acc[SA_MAXD], q);
         } else {
-          const cx<double> x0 = reinterpret_cast<const cx<double>*>(A.xk)[g];
+          const cx<double> x0 = xk[e];
           const cx<double> hs = 2.0 * (kin + vg * uu) +
                                 (4.0 * P.alpha) * (abs2(x0) * uu + (2.0 * redot(x0, uu)) * x0) + A.delta * uu;
-          out[g] = cvt<T>(hs);
+          stc<T>(A.out, g, cvt<T>(hs));
         }
       }
     block_reduce<SA_COUNT_SUM, 1>(acc, red);
     if (threadIdx.x == 0) {
-      double* o = P.partF + (int64_t)tile * SA_COUNT;
+      const int64_t o = (int64_t)tile * SA_COUNT;
 #pragma unroll
-      for (int i = 0; i < SA_COUNT; ++i) o[i] = acc[i];
+      for (int i = 0; i < SA_COUNT; ++i) gst<double>(P.partF, o + i, acc[i]);
     }
   }
 }
@@ -78,9 +86,9 @@ __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ 
                                                     const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[SA_COUNT * 16];
-  const ProbDev& P = probs[0];
+  const ProbDev P = probs[0];     // local copy: one batch of loads
   const int tile = blockIdx.x;
-  const int n = P.n[role_axis(ROLE, P.dim)];
+  const int n = pick3(P.n, role_axis(ROLE, P.dim));
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   switch (n) {
     case 16: apply_tile<16, ROLE, T>(P, A, tile, lds, tw, red); break;

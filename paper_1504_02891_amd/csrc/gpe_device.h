@@ -12,6 +12,71 @@ struct alignas(2 * sizeof(T)) cx {
   T re, im;
 };
 
+// Global-memory access through pointers read from descriptors.  Such
+// pointers are generic to the compiler, and generic (flat) accesses wait on
+// both the vector-memory and the LDS counters; the cast makes them plain
+// global loads and stores that can be issued back to back.
+// Complex values move as two-element vectors (one 8- or 16-byte access).
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> struct GAccess {
+  static __device__ __forceinline__ T load(const void* p, int64_t i) { return ((gptr<const T>)p)[i]; }
+  static __device__ __forceinline__ void store(void* p, int64_t i, T v) { ((gptr<T>)p)[i] = v; }
+};
+template <typename U> struct GAccess<cx<U>> {
+  typedef U v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ cx<U> load(const void* p, int64_t i) {
+    const v2 r = ((gptr<const v2>)p)[i];
+    return cx<U>{r.x, r.y};
+  }
+  static __device__ __forceinline__ void store(void* p, int64_t i, cx<U> v) {
+    v2 r;
+    r.x = v.re;
+    r.y = v.im;
+    ((gptr<v2>)p)[i] = r;
+  }
+};
+template <typename T> __device__ __forceinline__ T gld(const void* p, int64_t i) { return GAccess<T>::load(p, i); }
+template <typename T> __device__ __forceinline__ void gst(void* p, int64_t i, T v) { GAccess<T>::store(p, i, v); }
+
+// Makes the value of `x` available in a scalar register at this point, so
+// that the load behind it is issued here and later uses read the register.
+// Applied to the descriptor fields a kernel needs, right after reading them,
+// it turns a chain of lazily issued scalar loads (one wait per branch that
+// first needs a field) into one batch with one wait.  Only for values that
+// are uniform across the wavefront.
+template <typename T> __device__ __forceinline__ void pin_reg(T& x) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "pin_reg: 32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    uint32_t w = __builtin_bit_cast(uint32_t, x);
+    asm volatile("" : "+s"(w));
+    x = __builtin_bit_cast(T, w);
+  } else {
+    uint64_t w = __builtin_bit_cast(uint64_t, x);
+    asm volatile("" : "+s"(w));
+    x = __builtin_bit_cast(T, w);
+  }
+}
+
+// One load per 64-byte line of a struct, all issued together and completed
+// here: later reads of any of its fields (issued lazily by the compiler, one
+// branch at a time) then hit the cache instead of each waiting on memory.
+template <typename T> __device__ __forceinline__ void touch_lines(const T* p) {
+  constexpr int L = (int)((sizeof(T) + 63) / 64);
+  uint32_t w[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) w[i] = ((gptr<const uint32_t>)p)[16 * i];
+#pragma unroll
+  for (int i = 0; i < L; ++i) asm volatile("" ::"v"(w[i]));
+}
+
+// Element i of a 2- or 3-array with i known only at run time, by selects, so
+// that a local copy of a descriptor is never indexed dynamically (which would
+// place it in scratch memory).
+template <typename T> __device__ __forceinline__ T sel2(const T* a, int i) { return i ? a[1] : a[0]; }
+template <typename T> __device__ __forceinline__ T pick3(const T* a, int i) {
+  return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+
 template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
 template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
@@ -231,23 +296,101 @@ __device__ __forceinline__ void line_fft(cx<T>* v, int t, int lane, const LdsMap
 
 // Per-workgroup twiddle table exp(-2 pi i m / N) from the 1024-entry table.
 // Callers issue it before a barrier that precedes the first stage using it.
+// The workgroup has at least N/8 threads (lanes x N/8), so eight rounds
+// cover the table.  fetch issues the loads, store writes the LDS table;
+// callers put their other loads in between so that all go out together.
 template <int N, typename T>
-__device__ __forceinline__ void load_twiddles(cx<T>* twl, const cx<T>* tw1024) {
-  for (int m = threadIdx.x; m < N; m += blockDim.x) twl[m] = tw1024[m * (kTwN / N)];
-}
+struct TwiddleFetch {
+  cx<T> w[8];
+  __device__ __forceinline__ void fetch(const cx<T>* tw1024) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int m = min((int)(threadIdx.x + k * blockDim.x), N - 1);
+      w[k] = gld<cx<T>>(tw1024, m * (kTwN / N));
+    }
+  }
+  __device__ __forceinline__ void store(cx<T>* twl) const {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int m = threadIdx.x + k * blockDim.x;
+      if (m < N) twl[m] = w[k];
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
-// FP64 reductions: wavefront butterfly, then across the block's waves.
+// FP64 reductions: within a wavefront by DPP moves, then across the block's waves.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+// Cross-lane move of a double with DPP: lanes of rows outside ROWMASK (and
+// lanes whose source is outside the wavefront) receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, CTRL, ROWMASK, 0xf, false);
 }
-__device__ __forceinline__ double wave_max(double x) {
+// value of lane 63, in every lane
+__device__ __forceinline__ double lane63(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <int CTRL, int ROWMASK, int K>
+__device__ __forceinline__ void dpp_step(double* acc, unsigned maxmask) {
+  double u[K];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-  return x;
+  for (int i = 0; i < K; ++i) u[i] = dpp_d<CTRL, ROWMASK>(acc[i]);
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = ((maxmask >> i) & 1u) ? fmax(acc[i], u[i]) : acc[i] + u[i];
+}
+// Reduction over the 64 lanes of a full wavefront of K values at once (sums,
+// or maxima where bit i of `maxmask` is set; maxima of non-negative values).
+// Fixed combining order: lane pairs, quads, half rows, rows (mirrored
+// partners, so all lanes of a row agree bitwise), then row 0 into row 1 and
+// row 2 into row 3, then rows 0-1 into row 3.  The result is broadcast from
+// lane 63, so every lane, and every caller reducing the same values, gets
+// the same bits.  The steps are VALU moves: no LDS round trip.
+template <int K>
+__device__ __forceinline__ void wave_reduce_k(double* acc, unsigned maxmask) {
+  dpp_step<0xb1, 0xf, K>(acc, maxmask);    // quad_perm [1,0,3,2]
+  dpp_step<0x4e, 0xf, K>(acc, maxmask);    // quad_perm [2,3,0,1]
+  dpp_step<0x141, 0xf, K>(acc, maxmask);   // row_half_mirror
+  dpp_step<0x140, 0xf, K>(acc, maxmask);   // row_mirror
+  dpp_step<0x142, 0xa, K>(acc, maxmask);   // row_bcast:15 into rows 1, 3
+  dpp_step<0x143, 0xc, K>(acc, maxmask);   // row_bcast:31 into rows 2, 3
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = lane63(acc[i]);
+}
+
+// Fixed-order reduction of part[i*stride + s] over i < count, for slots
+// s < NSLOT (a max where bit s of `maxmask` is set, else a sum), by one
+// wavefront: lane l accumulates i = l, l+64, l+128, ... in turn, then the
+// lanes are combined by wave_reduce_k.  Loads go out in batches of B per
+// lane (indices clamped, the extra values discarded).  Every lane of the
+// calling wavefront gets the result; every caller reducing the same
+// partials gets the same bits.
+template <int NSLOT>
+__device__ __forceinline__ void wave_reduce_partials(const double* part, int count, int stride, unsigned maxmask,
+                                                     double* acc) {
+  constexpr int B = NSLOT <= 4 ? 8 : 4;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;
+  for (int b0 = 0; b0 < count; b0 += 64 * B) {
+    double v[B][NSLOT];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int64_t i = min(b0 + l + 64 * j, count - 1);
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) v[j][s] = gld<double>(part, i * stride + s);
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (b0 + l + 64 * j < count)
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s)
+          acc[s] = ((maxmask >> s) & 1u) ? fmax(acc[s], v[j][s]) : acc[s] + v[j][s];
+  }
+  wave_reduce_k<NSLOT>(acc, maxmask);
 }
 
 // Reduce NS sums followed by NM maxima over the block; thread 0 gets results
@@ -255,10 +398,7 @@ __device__ __forceinline__ double wave_max(double x) {
 template <int NS, int NM>
 __device__ __forceinline__ void block_reduce(double* acc, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) acc[i] = wave_sum(acc[i]);
-#pragma unroll
-  for (int i = NS; i < NS + NM; ++i) acc[i] = wave_max(acc[i]);
+  wave_reduce_k<NS + NM>(acc, ((1u << NM) - 1u) << NS);
   __syncthreads();
   if (lane == 0)
 #pragma unroll

@@ -41,6 +41,9 @@ enum Role { R_FIRST = 0, R_MID = 1, R_FINAL = 2, R_SOLO = 3 };
 enum Mode : int32_t { M_IDLE = 0, M_F = 1, M_W = 2, M_OUTER = 3 };
 // Solver phases.
 enum Phase : int32_t { PH_INIT = 0, PH_ALG1 = 1, PH_OUTER = 2, PH_INNER = 3, PH_DONE = 4 };
+// Where the scalar step after an evaluation runs (see the GPE_STEP_* values).
+enum StepAt : int32_t { STEP_LAST_GROUP = 0, STEP_KERNEL = 1 };
+
 // Source of the point an M_OUTER evaluation starts from.
 enum OuterSrc : int32_t { SRC_XK = 0, SRC_XK_PLUS_S = 1, SRC_XF = 2 };
 
@@ -53,7 +56,7 @@ struct ProbDev {
   int32_t tiles[3];      // tiles (blocks) per pass along axis 0, 1, 2
   int32_t lanes[3];      // lines per tile in each pass
   int32_t has_v;         // 1: read v_arr, 0: separable v_axis tables
-  int32_t fuse_step;     // 1: the final pass's last workgroup runs the scalar step
+  int32_t step_at;       // StepAt: where the scalar step runs
   double lo[3], h[3], len[3];
   double beta, omega, hvol, sqrt_hvol, alpha;
   const double* v_arr;   // explicit V (float64), or null
@@ -95,7 +98,9 @@ struct SolverState {
   double tol, tau0, rho1, eta, sigma, renorm_tol;
   double eta1, eta2, gshrink, ggrow, delta_min, delta_max;
   int32_t k_init, k_sub, m_max, max_iter;
+  int32_t pad4, pad5;                      // whole 16-byte words (read with 16-byte loads)
 };
+static_assert(sizeof(SolverState) % 16 == 0, "SolverState is read in 16-byte words");
 
 // LDS elements (complex) a tile of `lanes` lines of n points needs for its
 // line data (must match LdsMap in the device code).

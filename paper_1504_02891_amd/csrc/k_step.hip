@@ -5,17 +5,24 @@
 
 namespace gpe {
 
-// Scalar step as its own launch (one workgroup of 64 per problem), for
-// comparison with the step fused into the final pass.
-__global__ void __launch_bounds__(64) k_step(const ProbDev* __restrict__ probs, SolverState* states, int prec64) {
-  __shared__ double red[SF_COUNT];
-  const ProbDev& P = probs[blockIdx.x];
-  SolverState& S = states[blockIdx.x];
-  if (S.mode == M_IDLE) return;
+// Scalar step as its own launch (one wavefront per problem).  The state is
+// copied in with one batch of loads, advanced in registers by one thread and
+// written back whole.
+__global__ void __launch_bounds__(64) k_step(const ProbDev* __restrict__ probs, SolverState* __restrict__ states,
+                                             int prec64) {
+  ProbDev P = probs[blockIdx.x];
+  pin_reg(P.part1); pin_reg(P.partF); pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
+  pin_reg(P.dim); pin_reg(P.sqrt_hvol);
+  SolverState L = states[blockIdx.x];
+  touch_lines(states + blockIdx.x);
+  if (L.mode == M_IDLE) return;
   double r1[S1_COUNT], rf[SF_COUNT];
-  reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1, red);
-  reduce_partials<SF_COUNT>(P.partF, P.tiles[P.dim - 1], SF_COUNT, 1u << SF_SMAX, rf, red);
-  if (threadIdx.x == 0) step_logic(P, S, r1, rf, prec64);
+  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1);
+  wave_reduce_partials<SF_COUNT>(P.partF, pick3(P.tiles, P.dim - 1), SF_COUNT, 1u << SF_SMAX, rf);
+  if (threadIdx.x == 0) {
+    step_logic(P, L, r1, rf, prec64);
+    states[blockIdx.x] = L;
+  }
 }
 
 

@@ -17,19 +17,20 @@ namespace gpe {
 __device__ __forceinline__ int role_axis(int role, int dim) {
   return role == R_FIRST || role == R_SOLO ? 0 : (role == R_MID ? 1 : dim - 1);
 }
-__device__ __forceinline__ int64_t pass_cols(const ProbDev& P, int ax) { return P.m / P.n[ax]; }
 
 // Thread layout of a tile: `lanes` lines of N points, TL threads per line.
 // The grid coordinates of a line (all but the one along the pass axis) are
-// decoded once per tile with 32-bit arithmetic.
+// decoded once per tile with 32-bit arithmetic.  Inactive threads of a
+// partial last tile address line 0, so that every load is unconditional;
+// only their stores are skipped.  `P` is a local copy of the descriptor.
 template <int N>
 struct Tile {
   static constexpr int E = Plan<N>::E, TL = N / E;
   int lanes, lane, t, ax;
-  int c[3];          // coordinates of the line's first point
+  int c0, c1, c2;    // coordinates of the line's first point (x, y, z)
   bool act;
   int64_t base, st;
-  double vcol;       // potential of the fixed coordinates (separable V)
+  double va[3];      // separable V tables at the line's fixed coordinates
   LdsMap mp;
   __device__ __forceinline__ Tile(const ProbDev& P, int ax_, bool strided, int tile) {
     ax = ax_;
@@ -37,31 +38,51 @@ struct Tile {
     if (strided) { lane = threadIdx.x % lanes; t = threadIdx.x / lanes; }
     else { lane = threadIdx.x / TL; t = threadIdx.x % TL; }
     const int col = tile * lanes + lane;
-    act = col < (int)pass_cols(P, ax);
+    const int ncols = (int)(P.m / pick3(P.n, ax));
+    act = col < ncols;
     const int cc = act ? col : 0;
     const int n0 = P.n[0], n1 = P.n[1];
-    if (ax == 0) { c[0] = 0; c[1] = cc % n1; c[2] = cc / n1; }
-    else if (ax == 1) { c[0] = cc % n0; c[1] = 0; c[2] = cc / n0; }
-    else { c[0] = cc % n0; c[1] = cc / n0; c[2] = 0; }
-    base = (int64_t)c[0] + (int64_t)c[1] * P.stride[1] + (int64_t)c[2] * P.stride[2];
-    st = P.stride[ax];
-    vcol = 0.0;
-    if (!P.has_v)
-      for (int a = 0; a < P.dim; ++a)
-        if (a != ax) vcol += P.v_axis[a * kMaxN + c[a]];
+    if (ax == 0) { c0 = 0; c1 = cc % n1; c2 = cc / n1; }
+    else if (ax == 1) { c0 = cc % n0; c1 = 0; c2 = cc / n0; }
+    else { c0 = cc % n0; c1 = cc / n0; c2 = 0; }
+    base = (int64_t)c0 + (int64_t)c1 * P.stride[1] + (int64_t)c2 * P.stride[2];
+    st = pick3(P.stride, ax);
+    // separable V: the tables at the line's fixed coordinates (unconditional
+    // loads, in bounds of the [3][kMaxN] table; combined in pot_value)
+    va[0] = gld<double>(P.v_axis, c0);
+    va[1] = gld<double>(P.v_axis, kMaxN + c1);
+    va[2] = gld<double>(P.v_axis, 2 * kMaxN + c2);
     mp.lanes = lanes;
     mp.strided = strided;
   }
   __device__ __forceinline__ int pos(int e) const { return t + e * TL; }
   __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)(t + e * TL) * st; }
-  __device__ __forceinline__ double pot(const ProbDev& P, int e) const {
-    return P.has_v ? P.v_arr[g(e)] : vcol + P.v_axis[ax * kMaxN + pos(e)];
+  // Potential at the thread's elements in two steps, so that the loads join
+  // the tile's batch and the arithmetic waits until the values are used:
+  // pot_load fetches the explicit V or this axis' table entries, pot_value
+  // adds the other axes' entries.
+  __device__ __forceinline__ void pot_load(const ProbDev& P, double* vp) const {
+    if (P.has_v) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_arr, g(e));
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_axis, ax * kMaxN + pos(e));
+    }
+  }
+  __device__ __forceinline__ double pot_value(const ProbDev& P, double vpe) const {
+    if (P.has_v) return vpe;
+    double vcol = 0.0;
+    if (ax != 0) vcol += va[0];
+    if (ax != 1 && P.dim > 1) vcol += va[1];
+    if (ax != 2 && P.dim > 2) vcol += va[2];
+    return vcol + vpe;
   }
   // Omega * (coordinate entering this axis' first-derivative multiplier)
   __device__ __forceinline__ double rot(const ProbDev& P) const {
     if (P.dim < 2 || P.omega == 0.0) return 0.0;
-    if (ax == 0) return P.omega * (P.lo[1] + P.h[1] * (double)c[1]);    // + Omega y
-    if (ax == 1) return -P.omega * (P.lo[0] + P.h[0] * (double)c[0]);   // - Omega x
+    if (ax == 0) return P.omega * (P.lo[1] + P.h[1] * (double)c1);    // + Omega y
+    if (ax == 1) return -P.omega * (P.lo[0] + P.h[0] * (double)c0);   // - Omega x
     return 0.0;
   }
 };
@@ -82,7 +103,7 @@ __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const T
   cx<CT>* data = lds + N;
   line_fft<N, false>(v, T.t, T.lane, T.mp, data, twl);
   const CT rc = (CT)T.rot(P);
-  const CT tpl = (CT)(6.283185307179586477 / P.len[ax]);
+  const CT tpl = (CT)(6.283185307179586477 / pick3(P.len, ax));
   const CT inv_n = (CT)1 / (CT)N;
 #pragma unroll
   for (int e = 0; e < Tile<N>::E; ++e) {
@@ -92,66 +113,42 @@ __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const T
   line_fft<N, true>(v, T.t, T.lane, T.mp, data, twl);
 }
 
-// Deterministic reduction of part[i*stride + s], i < count, for slots
-// s < NSLOT (slot s is a max when bit s of `maxmask` is set, else a sum),
-// done by the workgroup's first wavefront: lane l takes i = l, l+64, ... in
-// order, then a butterfly.  All loads of a lane are independent (one memory
-// round trip).  The final pass and the scalar step both use this order, so
-// values derived from the same partials agree bitwise.  Every thread gets
-// the result.
+// One slot of the fixed-order reduction (the same bits as that slot of the
+// multi-slot call), computed by every wavefront of the caller on its own.
+__device__ __forceinline__ double wave_reduce_slot(const double* part, int count, int stride, int slot,
+                                                   bool is_max) {
+  double a[1];
+  wave_reduce_partials<1>(part + slot, count, stride, is_max ? 1u : 0u, a);
+  return a[0];
+}
+// Fixed-order reduction for a whole workgroup: the first wavefront reduces,
+// every thread gets the result through `red`.
 template <int NSLOT>
 __device__ __forceinline__ void reduce_partials(const double* part, int count, int stride, unsigned maxmask,
                                                 double* out, double* red) {
   if (threadIdx.x < 64) {
-    double acc[NSLOT];
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;
-    for (int i = threadIdx.x; i < count; i += 64) {
-#pragma unroll
-      for (int s = 0; s < NSLOT; ++s) {
-        const double v = part[(int64_t)i * stride + s];
-        acc[s] = ((maxmask >> s) & 1u) ? fmax(acc[s], v) : acc[s] + v;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) acc[s] = ((maxmask >> s) & 1u) ? wave_max(acc[s]) : wave_sum(acc[s]);
+    wave_reduce_partials<NSLOT>(part, count, stride, maxmask, out);
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int s = 0; s < NSLOT; ++s) red[s] = acc[s];
+      for (int s = 0; s < NSLOT; ++s) red[s] = out[s];
   }
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) out[s] = red[s];
   __syncthreads();
 }
-// one slot with the same arithmetic (slots are reduced independently, so
-// this equals slot `slot` of the multi-slot call bitwise)
 __device__ __forceinline__ double fixed_reduce(const double* part, int count, int stride, int slot,
                                                bool is_max, double* red) {
-  if (threadIdx.x < 64) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < count; i += 64) {
-      const double v = part[(int64_t)i * stride + slot];
-      a = is_max ? fmax(a, v) : a + v;
-    }
-    a = is_max ? wave_max(a) : wave_sum(a);
-    if (threadIdx.x == 0) red[0] = a;
-  }
-  __syncthreads();
-  const double r = red[0];
-  __syncthreads();
-  return r;
+  double r[1];
+  reduce_partials<1>(part + slot, count, stride, is_max ? 1u : 0u, r, red);
+  return r[0];
 }
 __device__ __forceinline__ double renorm_c(const SolverState& S, double ny) {
   return (S.force_norm || fabs(ny - 1.0) > S.renorm_tol) ? 1.0 / sqrt(ny) : 1.0;
 }
 
-template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, int64_t g) {
-  return reinterpret_cast<const cx<T>*>(p)[g];
-}
-template <typename T> __device__ __forceinline__ void stc(void* p, int64_t g, cx<T> v) {
-  reinterpret_cast<cx<T>*>(p)[g] = v;
-}
+template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, int64_t g) { return gld<cx<T>>(p, g); }
+template <typename T> __device__ __forceinline__ void stc(void* p, int64_t g, cx<T> v) { gst<cx<T>>(p, g, v); }
 
 // ---------------------------------------------------------------------------
 // Per-mode inputs (kept in registers for the whole pass), trial point and
@@ -167,7 +164,7 @@ struct FOps {
   const ProbDev& P; const SolverState& S;
   const void *xb, *gb; void *xo, *go;
   __device__ FOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
-    xb = P.xf[S.cur]; gb = P.gf[S.cur]; xo = P.xf[S.cur ^ 1]; go = P.gf[S.cur ^ 1];
+    xb = sel2(P.xf, S.cur); gb = sel2(P.gf, S.cur); xo = sel2(P.xf, S.cur ^ 1); go = sel2(P.gf, S.cur ^ 1);
   }
   __device__ __forceinline__ In load(int64_t g) const { return In{ld<TF>(xb, g), ld<TF>(gb, g)}; }
   __device__ __forceinline__ cx<double> trial(const In& in) const {
@@ -214,13 +211,15 @@ template <typename TW>
 struct WOps {
   struct In { cx<double> xk, gk; cx<TW> s, d; };
   const ProbDev& P; const SolverState& S;
-  const cx<double>*xk, *gk; const void *sb, *db; void *so, *dout;
+  const void *xk, *gk, *sb, *db; void *so, *dout;
   __device__ WOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
-    xk = reinterpret_cast<const cx<double>*>(P.xk);
-    gk = reinterpret_cast<const cx<double>*>(P.gk);
-    sb = P.s[S.cur]; db = P.d[S.cur]; so = P.s[S.cur ^ 1]; dout = P.d[S.cur ^ 1];
+    xk = P.xk;
+    gk = P.gk;
+    sb = sel2(P.s, S.cur); db = sel2(P.d, S.cur); so = sel2(P.s, S.cur ^ 1); dout = sel2(P.d, S.cur ^ 1);
   }
-  __device__ __forceinline__ In load(int64_t g) const { return In{xk[g], gk[g], ld<TW>(sb, g), ld<TW>(db, g)}; }
+  __device__ __forceinline__ In load(int64_t g) const {
+    return In{ld<double>(xk, g), ld<double>(gk, g), ld<TW>(sb, g), ld<TW>(db, g)};
+  }
   __device__ __forceinline__ cx<double> trial(const In& in) const {
     return S.pm1 * in.xk + S.p * cvt<double>(in.s) + S.q * (in.gk + cvt<double>(in.d));
   }
@@ -272,15 +271,17 @@ template <typename TF, typename TW>
 struct OOps {
   struct In { cx<double> y; };
   const ProbDev& P; const SolverState& S;
-  cx<double>*xk, *gk;
+  void *xk, *gk; const void *xf, *sc;
   __device__ OOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
-    xk = reinterpret_cast<cx<double>*>(P.xk);
-    gk = reinterpret_cast<cx<double>*>(P.gk);
+    xk = P.xk;
+    gk = P.gk;
+    xf = sel2(P.xf, S.cur);
+    sc = sel2(P.s, S.cur);
   }
   __device__ __forceinline__ In load(int64_t g) const {
-    if (S.src == SRC_XF) return In{cvt<double>(ld<TF>(P.xf[S.cur], g))};
-    if (S.src == SRC_XK_PLUS_S) return In{xk[g] + cvt<double>(ld<TW>(P.s[S.cur], g))};
-    return In{xk[g]};
+    if (S.src == SRC_XF) return In{cvt<double>(ld<TF>(xf, g))};
+    if (S.src == SRC_XK_PLUS_S) return In{ld<double>(xk, g) + cvt<double>(ld<TW>(sc, g))};
+    return In{ld<double>(xk, g)};
   }
   __device__ __forceinline__ cx<double> trial(const In& in) const { return in.y; }
   __device__ __forceinline__ void metrics1(const In&, cx<double> y, Acc1& a) const { a.ny += abs2(y); }
@@ -290,8 +291,8 @@ struct OOps {
     const double q = abs2(y);
     const cx<double> ay = 2.0 * (c * kin + vg * y);
     const cx<double> gy = ay + (4.0 * P.alpha * q) * y;
-    xk[g] = y;
-    gk[g] = gy;
+    stc<double>(xk, g, y);
+    stc<double>(gk, g, gy);
     stc<TW>(P.s[0], g, cx<TW>{0, 0});
     stc<TW>(P.d[0], g, cx<TW>{0, 0});
     a.s[SF_F] += 0.5 * redot(y, ay) + P.alpha * q * q;
@@ -302,70 +303,79 @@ struct OOps {
 };
 
 // ---------------------------------------------------------------------------
-// One tile of one pass for a given mode.
+// One tile of one pass for a given mode.  P and S are local copies (read once
+// at kernel entry, before any store).  Every input of the tile goes out as
+// one batch of loads: the trial point's arrays, the accumulator of the
+// earlier passes, the potential, the twiddle table and (final pass) the
+// first pass's norm partials.
 // ---------------------------------------------------------------------------
 template <int N, int ROLE, typename CT, class Ops>
 __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState& S, int tile, const Ops& ops,
                                             cx<CT>* lds, const cx<CT>* tw1024, double* red) {
   constexpr int E = Tile<N>::E;
   constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
+  constexpr bool EPI = (ROLE == R_FINAL || ROLE == R_SOLO);
   const int ax = role_axis(ROLE, P.dim);
   const Tile<N> T(P, ax, HAS_T, tile);
-  load_twiddles<N>(lds, tw1024);
-  cx<CT>* tacc = reinterpret_cast<cx<CT>*>(P.t);
-  // every input of the thread's elements in one batch of independent loads
+  TwiddleFetch<N, CT> twf;
+  twf.fetch(tw1024);
   typename Ops::In in[E];
   cx<CT> tv[E];
+  double vp[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if (T.act) {
-      in[e] = ops.load(T.g(e));
-      if constexpr (HAS_T) tv[e] = tacc[T.g(e)];
-    }
+    in[e] = ops.load(T.g(e));
+    if constexpr (HAS_T) tv[e] = ld<CT>(P.t, T.g(e));
   }
+  if constexpr (EPI) T.pot_load(P, vp);
+  double c = 1.0, n_hat = 1.0;
+  if constexpr (ROLE == R_FINAL) {
+    // every wavefront reduces the first pass's norm partials itself
+    const double ny = wave_reduce_slot(P.part1, P.tiles[0], S1_COUNT, S1_NY, false);
+    c = renorm_c(S, ny);
+    n_hat = c * c * ny;
+  }
+  twf.store(lds);
   cx<CT> v[E];
   Acc1 a1;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    cx<double> y{0.0, 0.0};
-    if (T.act) {
-      y = ops.trial(in[e]);
-      if constexpr (ROLE == R_FIRST || ROLE == R_SOLO) ops.metrics1(in[e], y, a1);
-    }
+    const cx<double> y = ops.trial(in[e]);
+    if constexpr (ROLE == R_FIRST || ROLE == R_SOLO)
+      if (T.act) ops.metrics1(in[e], y, a1);
     v[e] = cvt<CT>(y);
   }
-  double c = 1.0, n_hat = 1.0;
   if constexpr (ROLE == R_SOLO) {
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
     block_reduce<2, 1>(acc, red);
     __shared__ double bc;
     if (threadIdx.x == 0) {
       bc = acc[0];
-      P.part1[S1_NY] = acc[0]; P.part1[S1_NP2] = acc[1]; P.part1[S1_RMAX] = acc[2];
+      gst<double>(P.part1, S1_NY, acc[0]);
+      gst<double>(P.part1, S1_NP2, acc[1]);
+      gst<double>(P.part1, S1_RMAX, acc[2]);
     }
     __syncthreads();
     c = renorm_c(S, bc);
     n_hat = c * c * bc;
-  } else if constexpr (ROLE == R_FINAL) {
-    const double ny = fixed_reduce(P.part1, P.tiles[0], S1_COUNT, S1_NY, false, red);
-    c = renorm_c(S, ny);
-    n_hat = c * c * ny;
   }
   spectral_apply<N, CT>(P, ax, T, v, lds);
   if constexpr (ROLE == R_FIRST) {
     if (T.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) tacc[T.g(e)] = v[e];
+      for (int e = 0; e < E; ++e) stc<CT>(P.t, T.g(e), v[e]);
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
     block_reduce<2, 1>(acc, red);
     if (threadIdx.x == 0) {
-      double* o = P.part1 + (int64_t)tile * S1_COUNT;
-      o[S1_NY] = acc[0]; o[S1_NP2] = acc[1]; o[S1_RMAX] = acc[2];
+      const int64_t o = (int64_t)tile * S1_COUNT;
+      gst<double>(P.part1, o + S1_NY, acc[0]);
+      gst<double>(P.part1, o + S1_NP2, acc[1]);
+      gst<double>(P.part1, o + S1_RMAX, acc[2]);
     }
   } else if constexpr (ROLE == R_MID) {
     if (T.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) tacc[T.g(e)] = tv[e] + v[e];
+      for (int e = 0; e < E; ++e) stc<CT>(P.t, T.g(e), tv[e] + v[e]);
   } else {
     AccF af;
     if (T.act)
@@ -373,7 +383,7 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
       for (int e = 0; e < E; ++e) {
         cx<double> kin = cvt<double>(v[e]);
         if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
-        ops.final_(in[e], T.g(e), T.pot(P, e), kin, c, n_hat, af);
+        ops.final_(in[e], T.g(e), T.pot_value(P, vp[e]), kin, c, n_hat, af);
       }
     double acc[SF_COUNT];
 #pragma unroll
@@ -381,16 +391,16 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
     acc[SF_SMAX] = af.smax;
     block_reduce<SF_COUNT_SUM, 1>(acc, red);
     if (threadIdx.x == 0) {
-      double* o = P.partF + (int64_t)tile * SF_COUNT;
+      const int64_t o = (int64_t)tile * SF_COUNT;
 #pragma unroll
-      for (int i = 0; i < SF_COUNT; ++i) o[i] = acc[i];
+      for (int i = 0; i < SF_COUNT; ++i) gst<double>(P.partF, o + i, acc[i]);
     }
   }
 }
 
 // The last workgroup to finish a problem's final pass (ticket counter) runs
 // the scalar step of the solver on the reduced partial sums.
-__device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState& S, int ntiles, int prec64,
+__device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, int ntiles, int prec64,
                                              double* red) {
   __shared__ int is_last;
   if (threadIdx.x == 0) {
@@ -406,16 +416,42 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState& S, i
     is_last = last;
   }
   __syncthreads();
-  if (!is_last) return;
+  if (!is_last || threadIdx.x >= 64) return;
+  touch_lines(Sg);
   double r1[S1_COUNT], rf[SF_COUNT];
-  reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1, red);
-  reduce_partials<SF_COUNT>(P.partF, ntiles, SF_COUNT, 1u << SF_SMAX, rf, red);
-  if (threadIdx.x == 0) step_logic(P, S, r1, rf, prec64);
+  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1);
+  wave_reduce_partials<SF_COUNT>(P.partF, ntiles, SF_COUNT, 1u << SF_SMAX, rf);
+  if (threadIdx.x == 0) {
+    SolverState L = *Sg;
+    step_logic(P, L, r1, rf, prec64);
+    *Sg = L;
+  }
+}
+
+// The state fields the passes read.
+#define GPE_PASS_STATE_FIELDS(F) \
+  F(S.mode); F(S.cur); F(S.src); F(S.force_norm); F(S.p); F(S.q); F(S.pm1); F(S.n_b); F(S.a_b); \
+  F(S.delta); F(S.renorm_tol)
+
+// The descriptor fields the passes read, forced into registers at kernel
+// entry.
+__device__ __forceinline__ void pin_desc_fields(ProbDev& P) {
+  pin_reg(P.dim); pin_reg(P.n[0]); pin_reg(P.n[1]); pin_reg(P.n[2]);
+  pin_reg(P.stride[1]); pin_reg(P.stride[2]); pin_reg(P.m);
+  pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
+  pin_reg(P.has_v); pin_reg(P.step_at);
+  pin_reg(P.lo[0]); pin_reg(P.lo[1]); pin_reg(P.h[0]); pin_reg(P.h[1]);
+  pin_reg(P.len[0]); pin_reg(P.len[1]); pin_reg(P.len[2]);
+  pin_reg(P.omega); pin_reg(P.alpha);
+  pin_reg(P.v_arr); pin_reg(P.v_axis);
+  pin_reg(P.xf[0]); pin_reg(P.xf[1]); pin_reg(P.gf[0]); pin_reg(P.gf[1]);
+  pin_reg(P.s[0]); pin_reg(P.s[1]); pin_reg(P.d[0]); pin_reg(P.d[1]);
+  pin_reg(P.xk); pin_reg(P.gk); pin_reg(P.t); pin_reg(P.part1); pin_reg(P.partF);
 }
 
 // Dispatch on the problem's mode.  PREC64: every array float64.
 template <int N, int ROLE, bool PREC64>
-__device__ __forceinline__ void solver_dispatch(const ProbDev& P, SolverState& S, int tile, char* smem,
+__device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverState& S, int tile, char* smem,
                                                 const cx<double>* twd, const cx<float>* twf, double* red) {
   using TS = typename std::conditional<PREC64, double, float>::type;   // F/W storage and transforms
   const cx<TS>* tws = PREC64 ? reinterpret_cast<const cx<TS>*>(twd) : reinterpret_cast<const cx<TS>*>(twf);
@@ -431,6 +467,8 @@ __device__ __forceinline__ void solver_dispatch(const ProbDev& P, SolverState& S
   }
 }
 
+// `bmap` maps a workgroup to (problem, tile); null for a single problem
+// (workgroup b is tile b of problem 0).
 template <int ROLE, bool PREC64>
 __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__ probs,
                                                      SolverState* __restrict__ states,
@@ -439,11 +477,15 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
                                                      const cx<float>* __restrict__ twf) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[SF_COUNT * 16];
-  const int2 bm = bmap[blockIdx.x];
-  const ProbDev& P = probs[bm.x];
-  SolverState& S = states[bm.x];
+  const int2 bm = bmap ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+  // local copies, read in one batch: the fields the pass needs pinned in
+  // scalar registers
+  ProbDev P = probs[bm.x];
+  pin_desc_fields(P);
+  SolverState S = states[bm.x];
+  GPE_PASS_STATE_FIELDS(pin_reg);
   if (S.mode == M_IDLE) return;
-  const int n = P.n[role_axis(ROLE, P.dim)];
+  const int n = pick3(P.n, role_axis(ROLE, P.dim));
   switch (n) {
     case 16: solver_dispatch<16, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
     case 32: solver_dispatch<32, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
@@ -455,7 +497,8 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
     default: break;
   }
   if constexpr (ROLE == R_FINAL || ROLE == R_SOLO)
-    if (P.fuse_step) step_if_last(P, S, ROLE == R_SOLO ? 1 : P.tiles[P.dim - 1], PREC64 ? 1 : 0, red);
+    if (P.step_at == STEP_LAST_GROUP)
+      step_if_last(P, states + bm.x, ROLE == R_SOLO ? 1 : pick3(P.tiles, P.dim - 1), PREC64 ? 1 : 0, red);
 }
 
 }  // namespace gpe

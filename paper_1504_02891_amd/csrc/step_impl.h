@@ -7,7 +7,7 @@
 
 namespace gpe {
 
-__device__ inline void set_trial(SolverState& S) {
+__device__ __forceinline__ void set_trial(SolverState& S) {
   // Theorem 3.3 coefficients for the curve through the base point.
   const double t = S.t, a = S.a_b, n = S.n_b, ng = S.ng_b;
   const double den = 1.0 - t * t * a * a + t * t * n * ng;
@@ -17,7 +17,7 @@ __device__ inline void set_trial(SolverState& S) {
   S.mode = (S.phase == PH_INNER) ? M_W : M_F;
 }
 
-__device__ inline void finish(SolverState& S, int status, int src) {
+__device__ __forceinline__ void finish(SolverState& S, int status, int src) {
   S.phase = PH_DONE;
   S.mode = M_IDLE;
   S.status = status;
@@ -25,7 +25,7 @@ __device__ inline void finish(SolverState& S, int status, int src) {
   S.done = 1;
 }
 
-__device__ inline void end_alg1(SolverState& S, bool stopped) {
+__device__ __forceinline__ void end_alg1(SolverState& S, bool stopped) {
   if (S.alg == 1) {
     finish(S, stopped ? 0 : 1, SRC_XF);
     return;
@@ -37,7 +37,7 @@ __device__ inline void end_alg1(SolverState& S, bool stopped) {
   S.force_norm = 0;
 }
 
-__device__ inline void end_inner(SolverState& S) {
+__device__ __forceinline__ void end_inner(SolverState& S) {
   const double pred = S.k > 0 ? S.pred_acc : 0.0;
   const double rho = pred < 0.0 ? S.ared_acc / pred : -INFINITY;
   const bool acc = rho >= S.eta1;
@@ -53,7 +53,7 @@ __device__ inline void end_inner(SolverState& S) {
   S.force_norm = acc ? 1 : 0;
 }
 
-__device__ inline void step_logic(const ProbDev& P, SolverState& S, const double* r1, const double* rf,
+__device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, const double* r1, const double* rf,
                                   int prec64) {
   S.nfe++;
   if (prec64 || S.mode == M_OUTER) S.nfe64++;
