@@ -38,13 +38,16 @@ extern "C" {
 #define GPE_OK               0
 #define GPE_NOT_CONVERGED    1   /* iteration cap hit; outputs hold the last iterate */
 #define GPE_EINVAL          -1   /* null pointer, bad dim/box/sizes, Omega != 0 where not allowed, zero phi0 */
-#define GPE_EUNSUPPORTED    -2   /* n not a power of two in [16, 1024], or an unsupported combination */
+#define GPE_EUNSUPPORTED    -2   /* n not a power of two in [16, 1024] ([16, 512] for GPE_BC_SINE),
+                                    or an unsupported combination */
 #define GPE_ENOMEM          -3   /* device allocation failed */
 #define GPE_EDEVICE         -4   /* HIP runtime error (see gpe_last_error) */
 #define GPE_ENONFINITE      -5   /* a reduction became NaN/Inf (bad V, phi0 or divergence) */
 
 /* ---- enumerations ------------------------------------------------------ */
 #define GPE_BC_FOURIER       0   /* periodic, Fourier pseudospectral (§2.3) */
+#define GPE_BC_SINE          1   /* homogeneous Dirichlet, sine pseudospectral (§2.2, DST-I);
+                                    Omega must be 0 */
 
 #define GPE_PREC_FP64        0   /* every array and FFT in float64 */
 #define GPE_PREC_MIXED       1   /* FP32 FFT/pointwise bulk, FP64 reductions, scalars and outer Newton state */
@@ -62,11 +65,14 @@ extern "C" {
 /* ---- problem ------------------------------------------------------------ */
 typedef struct gpe_problem {
     int32_t dim;          /* 1, 2 or 3 */
-    int32_t bc;           /* GPE_BC_FOURIER */
-    int32_t n[3];         /* points per axis (x, y, z); entries beyond dim ignored */
+    int32_t bc;           /* GPE_BC_FOURIER or GPE_BC_SINE */
+    int32_t n[3];         /* per axis (x, y, z), entries beyond dim ignored.  Fourier: n periodic
+                             points x_j = lo + j h, j < n.  Sine: n intervals, n-1 interior
+                             points x_j = lo + j h, 0 < j < n.  h = (hi - lo)/n.  Arrays hold
+                             the points of every axis, x fastest */
     double lo[3], hi[3];  /* box U = prod (lo_i, hi_i), lo_i < hi_i */
     double beta;          /* interaction constant */
-    double omega;         /* rotation speed; must be 0 when dim == 1 */
+    double omega;         /* rotation speed; must be 0 when dim == 1 or bc is GPE_BC_SINE */
     double gamma[3];      /* harmonic trap V = 1/2 sum gamma_i^2 x_i^2 (§1) */
     double lattice_amp;   /* optical lattice A * sum sin^2(k x_i) (§4.2, §4.4); 0 = none */
     double lattice_k;     /* k of the lattice (pi/4 in the paper) */
@@ -92,7 +98,12 @@ typedef struct gpe_options {
     int32_t use_graph;    /* 1: replay chunks as a captured hipGraph; 0: plain launches */
     int32_t profile;      /* k > 0: time every k-th launch of the last-axis pass with HIP events
                              (plain launches instead of a graph); 0: off */
-    int32_t reserved0;
+    int32_t real_field;   /* -1 (default): real arithmetic when Omega = 0 for every problem and
+                             every phi0 has a zero imaginary part; 1: real arithmetic (Omega must
+                             be 0); 0: complex.  In real arithmetic the imaginary parts are
+                             dropped after every evaluation, so the iterates stay exactly real
+                             (the method on the unit sphere of R^M); otherwise rounding noise in
+                             them can grow and lead the iteration to a complex stationary state */
     int32_t threads[3];   /* workgroup size of the x, y, z passes (0 = built-in choice);
                              a multiple of 64 and of n/8, at most 256 */
     int32_t step_at;      /* where the scalar step of the solver runs (GPE_STEP_*) */
@@ -198,7 +209,8 @@ int gpe_solve_batched(gpe_ctx* ctx, int32_t count, const gpe_problem* probs,
  * axis on the same box (coarse points are every other fine point); per axis
  * the spectrum is zero-padded and the coarse Nyquist coefficient split half
  * and half between +n and -n.  phi_c, phi_f: DEVICE complex128 arrays.
- * fine must equal coarse with every n doubled.
+ * fine must equal coarse with every n doubled.  Fourier problems only
+ * (GPE_EUNSUPPORTED for GPE_BC_SINE).
  */
 int gpe_prolong(gpe_ctx* ctx, const gpe_problem* coarse, const gpe_problem* fine,
                 const void* phi_c, void* phi_f);
@@ -208,7 +220,7 @@ int gpe_prolong(gpe_ctx* ctx, const gpe_problem* coarse, const gpe_problem* fine
  * level, coarse problem given), each level solved by gpe_solve_batched for
  * all `count` problems, coarse levels to `level_tol`, the finest to opts->tol.
  * phi0s[i]: DEVICE complex128 initial data on the coarse grid (read only);
- * phis[i]: DEVICE complex128 outputs on the finest grid.
+ * phis[i]: DEVICE complex128 outputs on the finest grid.  Fourier problems only.
  */
 int gpe_solve_cascadic(gpe_ctx* ctx, int32_t count, const gpe_problem* coarse,
                        int32_t nlevels, double level_tol, const gpe_options* opts,

@@ -19,6 +19,7 @@ GPE_EDEVICE = -4
 GPE_ENONFINITE = -5
 
 GPE_BC_FOURIER = 0
+GPE_BC_SINE = 1
 GPE_PREC_FP64 = 0
 GPE_PREC_MIXED = 1
 GPE_ALG1 = 1
@@ -49,7 +50,7 @@ class Options(C.Structure):
                 ("gamma_grow", C.c_double),
                 ("delta0", C.c_double), ("delta_min", C.c_double), ("delta_max", C.c_double),
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("reserved0", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32)]
+                ("real_field", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -52,7 +52,7 @@ def problem_struct(p, v=None):
     ``v``: optional CUDA float64 tensor with the potential on the grid."""
     s = N.Problem()
     s.dim = int(p.dim)
-    s.bc = N.GPE_BC_FOURIER
+    s.bc = {"fourier": N.GPE_BC_FOURIER, "sine": N.GPE_BC_SINE}[getattr(p, "bc", "fourier")]
     for i in range(3):
         s.n[i] = int(p.n[i]) if i < p.dim else 1
         s.lo[i] = float(p.lo[i]) if i < p.dim else 0.0
@@ -62,9 +62,9 @@ def problem_struct(p, v=None):
     s.omega = float(p.omega)
     s.lattice_amp = float(getattr(p, "lattice_amp", 0.0))
     s.lattice_k = float(getattr(p, "lattice_k", math.pi / 4))
+    if v is not None:
+        _dev_tensor(v, torch.float64, "v", p)
     s.v = C.c_void_p(v.data_ptr()) if v is not None else None
-    if getattr(p, "bc", "fourier") != "fourier":
-        s.bc = 1  # rejected by the library (sine transform not exported)
     return s
 
 
@@ -92,12 +92,24 @@ def options(**kw):
     return o
 
 
-def _dev_tensor(t, dtype, name):
+def _dev_tensor(t, dtype, name, p=None):
     if not (isinstance(t, torch.Tensor) and t.is_cuda):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if p is not None and t.numel() != grid_points(p):
+        raise ValueError(f"{name} has {t.numel()} elements; the grid of the problem has {grid_points(p)}")
     return t
+
+
+def grid_points(p):
+    """Number of grid values of a problem (the library reads exactly this many):
+    n per axis (Fourier) or n - 1 interior points per axis (sine)."""
+    sine = getattr(p, "bc", "fourier") == "sine"
+    m = 1
+    for i in range(int(p.dim)):
+        m *= int(p.n[i]) - (1 if sine else 0)
+    return m
 
 
 SCALAR_NAMES = ("energy", "mu", "resid", "norm2", "rms_x", "rms_y", "rms_z", "max_dens",
@@ -105,10 +117,10 @@ SCALAR_NAMES = ("energy", "mu", "resid", "norm2", "rms_x", "rms_y", "rms_z", "ma
 
 
 def apply_h(p, phi, precision="fp64", v=None):
-    """H(phi) phi on the Fourier grid; returns (h_phi, scalars dict)."""
+    """H(phi) phi on the problem's grid; returns (h_phi, scalars dict)."""
     prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
     dt = torch.complex128 if prec == N.GPE_PREC_FP64 else torch.complex64
-    _dev_tensor(phi, dt, "phi")
+    _dev_tensor(phi, dt, "phi", p)
     out = torch.empty_like(phi)
     sc = (C.c_double * 10)()
     ps = problem_struct(p, v)
@@ -119,8 +131,8 @@ def apply_h(p, phi, precision="fp64", v=None):
 
 def hess_vec(p, x_k, s, delta, v=None):
     """A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s (X units)."""
-    _dev_tensor(x_k, torch.complex128, "x_k")
-    _dev_tensor(s, torch.complex128, "s")
+    _dev_tensor(x_k, torch.complex128, "x_k", p)
+    _dev_tensor(s, torch.complex128, "s", p)
     out = torch.empty_like(s)
     ps = problem_struct(p, v)
     _check(N.lib().gpe_hess_vec(context(s.device.index), C.byref(ps), C.c_void_p(x_k.data_ptr()),
@@ -143,7 +155,7 @@ def retract(x, g, tau):
 
 def solve(p, phi0, v=None, **opts):
     """Ground state from phi0 (complex128 CUDA tensor); returns (phi, result dict)."""
-    _dev_tensor(phi0, torch.complex128, "phi0")
+    _dev_tensor(phi0, torch.complex128, "phi0", p)
     phi = phi0.clone()
     res = N.Result()
     ps = problem_struct(p, v)
@@ -158,7 +170,7 @@ def solve_batched(probs, phi0s, **opts):
     n = len(probs)
     phis = []
     for i, t in enumerate(phi0s):
-        _dev_tensor(t, torch.complex128, f"phi0s[{i}]")
+        _dev_tensor(t, torch.complex128, f"phi0s[{i}]", probs[i])
         phis.append(t.clone())
     pa = (N.Problem * n)(*[problem_struct(p) for p in probs])
     ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in phis])
@@ -170,7 +182,7 @@ def solve_batched(probs, phi0s, **opts):
 
 
 def prolong(p_coarse, p_fine, phi_c):
-    _dev_tensor(phi_c, torch.complex128, "phi_c")
+    _dev_tensor(phi_c, torch.complex128, "phi_c", p_coarse)
     shape = tuple(int(n) for n in reversed(p_fine.n[: p_fine.dim]))
     out = torch.empty(shape, dtype=torch.complex128, device=phi_c.device)
     a, b = problem_struct(p_coarse), problem_struct(p_fine)
@@ -182,7 +194,7 @@ def prolong(p_coarse, p_fine, phi_c):
 def solve_cascadic(p_coarse_list, phi0s, nlevels, level_tol=1e-4, **opts):
     n = len(p_coarse_list)
     for i, t in enumerate(phi0s):
-        _dev_tensor(t, torch.complex128, f"phi0s[{i}]")
+        _dev_tensor(t, torch.complex128, f"phi0s[{i}]", p_coarse_list[i])
     fine = []
     for p in p_coarse_list:
         shape = tuple(int(k) << (nlevels - 1) for k in reversed(p.n[: p.dim]))

@@ -38,7 +38,7 @@ constexpr int kApplyThreads = 128;
 enum WsSlot {
   WS_PROB = 0, WS_STATE, WS_BMAP0, WS_BMAP1, WS_BMAP2, WS_VAXIS, WS_ARENA,
   WS_APPLY_T, WS_APPLY_PART, WS_APPLY_OUT, WS_APPLY_RPART, WS_APPLY_PROB, WS_APPLY_VAXIS,
-  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_COUNT
+  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_IMAG, WS_COUNT
 };
 
 }  // namespace
@@ -124,25 +124,33 @@ bool pow2_ok(int n) { return n >= 16 && n <= kMaxN && (n & (n - 1)) == 0; }
 int build_prob(const gpe_problem* p, ProbDev* d, double* vaxis) {
   if (!p || !d) return GPE_EINVAL;
   if (p->dim < 1 || p->dim > 3) return GPE_EINVAL;
-  if (p->bc != GPE_BC_FOURIER) return GPE_EUNSUPPORTED;
+  if (p->bc != GPE_BC_FOURIER && p->bc != GPE_BC_SINE) return GPE_EINVAL;
+  const bool sine = p->bc == GPE_BC_SINE;
   if (!std::isfinite(p->beta) || !std::isfinite(p->omega)) return GPE_EINVAL;
-  if (p->dim == 1 && p->omega != 0.0) return GPE_EINVAL;
+  if ((p->dim == 1 || sine) && p->omega != 0.0) return GPE_EINVAL;
   std::memset(d, 0, sizeof(*d));
   d->dim = p->dim;
+  d->bc = sine ? BC_SINE : BC_FOURIER;
   d->m = 1;
   double hvol = 1.0;
   for (int i = 0; i < 3; ++i) {
     if (i < p->dim) {
-      if (!pow2_ok(p->n[i])) return GPE_EUNSUPPORTED;
+      // sine: n intervals, n-1 interior points, transform of the 2n-point odd extension
+      if (!pow2_ok(p->n[i]) || (sine && 2 * p->n[i] > kMaxN)) return GPE_EUNSUPPORTED;
       if (!(p->lo[i] < p->hi[i]) || !std::isfinite(p->lo[i]) || !std::isfinite(p->hi[i])) return GPE_EINVAL;
-      d->n[i] = p->n[i];
+      const double box = p->hi[i] - p->lo[i];
+      d->n[i] = sine ? p->n[i] - 1 : p->n[i];
+      d->nl[i] = sine ? 2 * p->n[i] : p->n[i];
       d->lo[i] = p->lo[i];
-      d->len[i] = p->hi[i] - p->lo[i];
-      d->h[i] = d->len[i] / p->n[i];
+      d->h[i] = box / p->n[i];
+      d->x0[i] = sine ? p->lo[i] + d->h[i] : p->lo[i];
+      d->len[i] = sine ? 2.0 * box : box;
       hvol *= d->h[i];
     } else {
       d->n[i] = 1;
+      d->nl[i] = 1;
       d->lo[i] = 0.0;
+      d->x0[i] = 0.0;
       d->len[i] = 1.0;
       d->h[i] = 1.0;
     }
@@ -162,8 +170,8 @@ int build_prob(const gpe_problem* p, ProbDev* d, double* vaxis) {
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < kMaxN; ++j) {
         double v = 0.0;
-        if (i < p->dim && j < p->n[i]) {
-          const double x = d->lo[i] + d->h[i] * j;
+        if (i < p->dim && j < d->n[i]) {
+          const double x = d->x0[i] + d->h[i] * j;
           const double s = std::sin(p->lattice_k * x);
           v = 0.5 * p->gamma[i] * p->gamma[i] * x * x + p->lattice_amp * s * s;
         }
@@ -178,15 +186,15 @@ struct Geom {
   size_t smem;
 };
 
-// Tiling of a pass along axis `ax`: lines of N = n[ax] points, TL = N/kE
-// threads per line, `threads / TL` lines per workgroup.
+// Tiling of a pass along axis `ax`: transform lines of N = nl[ax] points,
+// TL = N/kE threads per line, `threads / TL` lines per workgroup.
 Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem) {
   Geom g;
-  const int N = d.n[ax];
+  const int N = d.nl[ax];
   const int TL = N / kE;
   g.threads = threads < TL ? TL : threads;
   g.lanes = g.threads / TL;
-  const int64_t cols = d.m / N;
+  const int64_t cols = d.m / d.n[ax];
   g.tiles = (int)((cols + g.lanes - 1) / g.lanes);
   // twiddle table (N entries) + line data
   g.smem = ((size_t)N + (size_t)gpe::lds_elems_host(N, g.lanes, strided)) * elem;
@@ -226,7 +234,7 @@ void set_default(gpe_options* o) {
   o->chunk = 64;
   o->use_graph = 1;
   o->profile = 0;
-  o->reserved0 = 0;
+  o->real_field = -1;
   o->threads[0] = o->threads[1] = o->threads[2] = 0;
   o->step_at = GPE_STEP_AUTO;
 }
@@ -322,6 +330,7 @@ int check_options(const gpe_options* o) {
     return GPE_EINVAL;
   if (o->chunk < 1 || o->chunk > 4096) return GPE_EINVAL;
   if (o->step_at < GPE_STEP_AUTO || o->step_at > GPE_STEP_KERNEL) return GPE_EINVAL;
+  if (o->real_field < -1 || o->real_field > 1) return GPE_EINVAL;
   return GPE_OK;
 }
 
@@ -355,7 +364,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     const int th = o.threads[ax];
     if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
     for (int i = 0; i < count && th != 0 && ax < dim; ++i)
-      if (th % (pd[i].n[ax] / kE) != 0) return GPE_EINVAL;
+      if (th % (pd[i].nl[ax] / kE) != 0) return GPE_EINVAL;
   }
   for (int i = 0; i < count; ++i)
     for (int ax = 0; ax < dim; ++ax) {
@@ -408,7 +417,36 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     L.off_pf = take((size_t)std::max(pd[i].tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
     L.off_ticket = take(64);
   }
+  // real arithmetic: forced (Omega = 0 required), or automatic when Omega = 0
+  // and every phi0 has a zero imaginary part (one max |Im| reduction each)
+  bool no_rotation = true;
+  for (int i = 0; i < count; ++i) no_rotation = no_rotation && probs[i].omega == 0.0;
+  if (o.real_field == 1 && !no_rotation) return GPE_EINVAL;
   CHK(begin_call(c));
+  int real = o.real_field == 1 ? 1 : 0;
+  if (o.real_field < 0 && no_rotation) {
+    std::vector<int> nb(count);
+    size_t tot = 0;
+    for (int i = 0; i < count; ++i) {
+      nb[i] = (int)std::min<int64_t>((pd[i].m + 255) / 256, 256);
+      tot += nb[i];
+    }
+    void *part, *hp;
+    CHK(ws_get(c, WS_IMAG, tot * sizeof(double), &part));
+    size_t at = 0;
+    for (int i = 0; i < count; ++i) {
+      launch_max_imag(c->s, nb[i], phis[i], pd[i].m, (double*)part + at);
+      at += nb[i];
+    }
+    HIPCHK(hipGetLastError());
+    CHK(pinned_get(c, tot * sizeof(double), &hp));
+    HIPCHK(hipMemcpyAsync(hp, part, tot * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    double mx = 0.0;
+    for (size_t k = 0; k < tot; ++k) mx = std::max(mx, ((const double*)hp)[k]);
+    real = mx == 0.0 ? 1 : 0;
+  }
+  for (int i = 0; i < count; ++i) pd[i].real = real;
   void *arena, *dprob, *dstate, *dvax, *dbm[3] = {nullptr, nullptr, nullptr};
   CHK(ws_get(c, WS_ARENA, off, &arena));
   CHK(ws_get(c, WS_PROB, sizeof(ProbDev) * count, &dprob));
@@ -735,6 +773,7 @@ int gpe_prolong(gpe_ctx* c, const gpe_problem* coarse, const gpe_problem* fine, 
   CHK(build_prob(coarse, &dc, nullptr));
   CHK(build_prob(fine, &df, nullptr));
   if (dc.dim != df.dim) return GPE_EINVAL;
+  if (dc.bc != BC_FOURIER || df.bc != BC_FOURIER) return GPE_EUNSUPPORTED;   // trigonometric prolongation
   for (int i = 0; i < dc.dim; ++i)
     if (df.n[i] != 2 * dc.n[i] || coarse->lo[i] != fine->lo[i] || coarse->hi[i] != fine->hi[i]) return GPE_EINVAL;
   CHK(begin_call(c));
@@ -759,6 +798,8 @@ int gpe_prolong(gpe_ctx* c, const gpe_problem* coarse, const gpe_problem* fine, 
 int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int32_t nlevels, double level_tol,
                        const gpe_options* opts, void* const* phi0s, void* const* phis, gpe_result* results) {
   if (!c || count < 1 || !coarse || nlevels < 1 || !opts || !phi0s || !phis || !results) return GPE_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (coarse[i].bc != GPE_BC_FOURIER) return GPE_EUNSUPPORTED;   // trigonometric prolongation
   std::vector<gpe_problem> lev(coarse, coarse + count);
   // per-level buffers: two ping-pong sets of `count` complex128 arrays
   size_t maxm = 0;

@@ -25,24 +25,24 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
     u[e] = ld<T>(A.in, Tl.g(e));
     if constexpr (HAS_T) tv[e] = ld<T>(P.t, Tl.g(e));
     if constexpr (EPI) xk[e] = A.kind == 1 ? ld<double>(A.xk, Tl.g(e)) : cx<double>{0.0, 0.0};
-    v[e] = u[e];
+    v[e] = cvt<T>(Tl.sgn(e) * cvt<double>(u[e]));
   }
   if constexpr (EPI) Tl.pot_load(P, vp);
   twf.store(lds);
   spectral_apply<N, T>(P, ax, Tl, v, lds);
   if constexpr (ROLE == R_FIRST) {
-    if (Tl.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) stc<T>(P.t, Tl.g(e), v[e]);
+    for (int e = 0; e < E; ++e)
+      if (Tl.inner(e)) stc<T>(P.t, Tl.g(e), v[e]);
   } else if constexpr (ROLE == R_MID) {
-    if (Tl.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) stc<T>(P.t, Tl.g(e), tv[e] + v[e]);
+    for (int e = 0; e < E; ++e)
+      if (Tl.inner(e)) stc<T>(P.t, Tl.g(e), tv[e] + v[e]);
   } else {
     double acc[SA_COUNT] = {};
-    if (Tl.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < E; ++e)
+      if (Tl.inner(e)) {
         const int64_t g = Tl.g(e);
         cx<double> kin = cvt<double>(v[e]);
         if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
@@ -60,8 +60,8 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
           for (int a = 0; a < 3; ++a) {
             if (a >= P.dim) break;
             const int ca = a == 0 ? Tl.c0 : (a == 1 ? Tl.c1 : Tl.c2);
-            const int ia = a == ax ? Tl.pos(e) : ca;
-            const double xa = P.lo[a] + P.h[a] * (double)ia;   // a is a compile-time index here
+            const int ia = a == ax ? Tl.idx(e) : ca;
+            const double xa = P.x0[a] + P.h[a] * (double)ia;   // a is a compile-time index here
             acc[SA_X2 + a] += xa * xa * q;
           }
           acc[SA_MAXD] = fmax(acc[SA_MAXD], q);
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ 
   __shared__ double red[SA_COUNT * 16];
   const ProbDev P = probs[0];     // local copy: one batch of loads
   const int tile = blockIdx.x;
-  const int n = pick3(P.n, role_axis(ROLE, P.dim));
+  const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   switch (n) {
     case 16: apply_tile<16, ROLE, T>(P, A, tile, lds, tw, red); break;

@@ -22,6 +22,8 @@ void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const voi
 void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* rpart, int nr, double* out);
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
                     double* part, double* coeffs);
+// per-block max |Im x_i| of a complex128 array (part[nblk])
+void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* part);
 void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
                          const void* twd);
 }  // namespace gpe

@@ -47,17 +47,30 @@ enum StepAt : int32_t { STEP_LAST_GROUP = 0, STEP_KERNEL = 1 };
 // Source of the point an M_OUTER evaluation starts from.
 enum OuterSrc : int32_t { SRC_XK = 0, SRC_XK_PLUS_S = 1, SRC_XF = 2 };
 
+// Boundary treatment of a problem (the GPE_BC_* values).
+enum Bc : int32_t { BC_FOURIER = 0, BC_SINE = 1 };
+
 // Per-problem description used on the device (read only in kernels).
+// Fourier: n[a] periodic points, each line transformed as it is.  Sine:
+// n[a] = N-1 interior points of N intervals; each line is transformed as its
+// odd extension of nl[a] = 2N points (zero at 0 and N, mirrored with a sign
+// change above N), which turns the Fourier multiplier into the sine
+// operator's.
 struct ProbDev {
   int32_t dim;
-  int32_t n[3];
+  int32_t n[3];          // array points per axis
+  int32_t nl[3];         // transform length per axis: n (Fourier) or 2(n+1) (sine)
+  int32_t bc;            // Bc
   int64_t stride[3];     // element stride of each axis: 1, nx, nx*ny
   int64_t m;             // number of grid points
   int32_t tiles[3];      // tiles (blocks) per pass along axis 0, 1, 2
   int32_t lanes[3];      // lines per tile in each pass
   int32_t has_v;         // 1: read v_arr, 0: separable v_axis tables
   int32_t step_at;       // StepAt: where the scalar step runs
-  double lo[3], h[3], len[3];
+  int32_t real;          // 1: drop the imaginary parts of every stored iterate and gradient
+  int32_t pad_r;
+  double lo[3], h[3], len[3];   // len: period of the transformed line (b-a, or 2(b-a) for sine)
+  double x0[3];          // coordinate of array index 0 (lo, or lo + h for sine)
   double beta, omega, hvol, sqrt_hvol, alpha;
   const double* v_arr;   // explicit V (float64), or null
   const double* v_axis;  // [3][kMaxN]: V = v_axis[0][x] + v_axis[1][y] + v_axis[2][z]

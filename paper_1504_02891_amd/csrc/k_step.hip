@@ -31,7 +31,7 @@ template <typename TF>
 __global__ void k_init(const ProbDev* probs, int pi, const cx<double>* __restrict__ phi0) {
   const ProbDev& P = probs[pi];
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
-    stc<TF>(P.xf[0], g, cvt<TF>(P.sqrt_hvol * phi0[g]));
+    stc<TF>(P.xf[0], g, realify(P, cvt<TF>(P.sqrt_hvol * phi0[g])));
     stc<TF>(P.gf[0], g, cx<TF>{0, 0});
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *P.ticket = 0;
@@ -103,6 +103,17 @@ __global__ void __launch_bounds__(64) k_apply_finalize(const ProbDev* probs, con
     out[8] = P.hvol * kin;
     out[9] = P.hvol * pot;
   }
+}
+
+// ---- largest |Im| of the initial data (choice of real arithmetic) ----
+__global__ void __launch_bounds__(256) k_max_imag(const cx<double>* __restrict__ x, int64_t m,
+                                                  double* __restrict__ part) {
+  __shared__ double red[16];
+  double a[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    a[0] = fmax(a[0], fabs(x[i].im));
+  block_reduce<0, 1>(a, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = a[0];
 }
 
 // ---- Cayley retraction (Theorem 3.3) on plain vectors ----
@@ -218,6 +229,9 @@ void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void*
   hipLaunchKernelGGL(k_retract_reduce, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, (const cx<double>*)g, m, part);
   hipLaunchKernelGGL(k_retract_apply, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, (const cx<double>*)g,
                      (cx<double>*)y, m, tau, part, nblk, coeffs);
+}
+void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* part) {
+  hipLaunchKernelGGL(k_max_imag, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, m, part);
 }
 void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
                          const void* twd) {

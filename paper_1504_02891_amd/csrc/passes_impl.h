@@ -18,22 +18,27 @@ __device__ __forceinline__ int role_axis(int role, int dim) {
   return role == R_FIRST || role == R_SOLO ? 0 : (role == R_MID ? 1 : dim - 1);
 }
 
-// Thread layout of a tile: `lanes` lines of N points, TL threads per line.
-// The grid coordinates of a line (all but the one along the pass axis) are
-// decoded once per tile with 32-bit arithmetic.  Inactive threads of a
-// partial last tile address line 0, so that every load is unconditional;
-// only their stores are skipped.  `P` is a local copy of the descriptor.
+// Thread layout of a tile: `lanes` lines of N transform points, TL threads
+// per line.  The grid coordinates of a line (all but the one along the pass
+// axis) are decoded once per tile with 32-bit arithmetic.  Inactive threads
+// of a partial last tile address line 0, so that every load is
+// unconditional; only their stores are skipped.  For a sine problem,
+// transform position p of the odd extension reads array index p-1 (p < N/2)
+// or N-1-p (p > N/2) with sign +1 / -1, and is zero at p = 0 and p = N/2;
+// only positions 1 .. N/2-1 ("inner") write results and enter reductions.
+// `P` is a local copy of the descriptor.
 template <int N>
 struct Tile {
   static constexpr int E = Plan<N>::E, TL = N / E;
   int lanes, lane, t, ax;
-  int c0, c1, c2;    // coordinates of the line's first point (x, y, z)
-  bool act;
+  int c0, c1, c2;    // array coordinates of the line's first point (x, y, z)
+  bool act, sine;
   int64_t base, st;
   double va[3];      // separable V tables at the line's fixed coordinates
   LdsMap mp;
   __device__ __forceinline__ Tile(const ProbDev& P, int ax_, bool strided, int tile) {
     ax = ax_;
+    sine = P.bc == BC_SINE;
     lanes = blockDim.x / TL;
     if (strided) { lane = threadIdx.x % lanes; t = threadIdx.x / lanes; }
     else { lane = threadIdx.x / TL; t = threadIdx.x % TL; }
@@ -56,7 +61,26 @@ struct Tile {
     mp.strided = strided;
   }
   __device__ __forceinline__ int pos(int e) const { return t + e * TL; }
-  __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)(t + e * TL) * st; }
+  // array index along the axis of transform position pos(e)
+  __device__ __forceinline__ int idx(int e) const {
+    const int p = pos(e);
+    if (!sine) return p;
+    const int h = N / 2;
+    const int i = p < h ? p - 1 : N - 1 - p;
+    return i < 0 ? 0 : (i > h - 2 ? h - 2 : i);
+  }
+  // sign of the odd extension at pos(e) (0 where it vanishes)
+  __device__ __forceinline__ double sgn(int e) const {
+    const int p = pos(e);
+    if (!sine) return 1.0;
+    return (p == 0 || p == N / 2) ? 0.0 : (p < N / 2 ? 1.0 : -1.0);
+  }
+  // pos(e) holds an array point of this line (not a mirror image)
+  __device__ __forceinline__ bool inner(int e) const {
+    const int p = pos(e);
+    return act && (!sine || (p > 0 && p < N / 2));
+  }
+  __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)idx(e) * st; }
   // Potential at the thread's elements in two steps, so that the loads join
   // the tile's batch and the arithmetic waits until the values are used:
   // pot_load fetches the explicit V or this axis' table entries, pot_value
@@ -67,7 +91,7 @@ struct Tile {
       for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_arr, g(e));
     } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_axis, ax * kMaxN + pos(e));
+      for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_axis, ax * kMaxN + idx(e));
     }
   }
   __device__ __forceinline__ double pot_value(const ProbDev& P, double vpe) const {
@@ -78,11 +102,12 @@ struct Tile {
     if (ax != 2 && P.dim > 2) vcol += va[2];
     return vcol + vpe;
   }
-  // Omega * (coordinate entering this axis' first-derivative multiplier)
+  // Omega * (coordinate entering this axis' first-derivative multiplier);
+  // rotation is Fourier only
   __device__ __forceinline__ double rot(const ProbDev& P) const {
     if (P.dim < 2 || P.omega == 0.0) return 0.0;
-    if (ax == 0) return P.omega * (P.lo[1] + P.h[1] * (double)c1);    // + Omega y
-    if (ax == 1) return -P.omega * (P.lo[0] + P.h[0] * (double)c0);   // - Omega x
+    if (ax == 0) return P.omega * (P.x0[1] + P.h[1] * (double)c1);    // + Omega y
+    if (ax == 1) return -P.omega * (P.x0[0] + P.h[0] * (double)c0);   // - Omega x
     return 0.0;
   }
 };
@@ -147,6 +172,11 @@ __device__ __forceinline__ double renorm_c(const SolverState& S, double ny) {
   return (S.force_norm || fabs(ny - 1.0) > S.renorm_tol) ? 1.0 / sqrt(ny) : 1.0;
 }
 
+// real arithmetic: the stored values keep their real parts only
+template <typename T> __device__ __forceinline__ cx<T> realify(const ProbDev& P, cx<T> v) {
+  return P.real ? cx<T>{v.re, (T)0} : v;
+}
+
 template <typename T> __device__ __forceinline__ cx<T> ld(const void* p, int64_t g) { return gld<cx<T>>(p, g); }
 template <typename T> __device__ __forceinline__ void stc(void* p, int64_t g, cx<T> v) { gst<cx<T>>(p, g, v); }
 
@@ -180,11 +210,11 @@ struct FOps {
   __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c,
                                          double n_hat, AccF& a) const {
     const cx<double> x = cvt<double>(in.x), gr = cvt<double>(in.g);
-    const cx<TF> ys = cvt<TF>(c * trial(in));
+    const cx<TF> ys = realify(P, cvt<TF>(c * trial(in)));
     const cx<double> y = cvt<double>(ys);
     const double q = abs2(y);
     const cx<double> ay = 2.0 * (c * kin + vg * y);
-    const cx<TF> gs = cvt<TF>(ay + (4.0 * P.alpha * q) * y);
+    const cx<TF> gs = realify(P, cvt<TF>(ay + (4.0 * P.alpha * q) * y));
     const cx<double> gy = cvt<double>(gs);
     stc<TF>(xo, g, ys);
     stc<TF>(go, g, gs);
@@ -238,10 +268,10 @@ struct WOps {
     const double qk = abs2(x0);
     const double al4 = 4.0 * P.alpha;
     const cx<double> axk = g0 - (al4 * qk) * x0;                     // A X_k
-    const cx<TW> ss = cvt<TW>(c * sn + (c - 1.0) * x0);               // renormalised S
+    const cx<TW> ss = realify(P, cvt<TW>(c * sn + (c - 1.0) * x0));   // renormalised S
     const cx<double> sv = cvt<double>(ss);
     const cx<double> as = c * (2.0 * (kin + vg * sn)) + (c - 1.0) * axk;  // A S
-    const cx<TW> ds = cvt<TW>(as + al4 * (qk * sv + (2.0 * redot(x0, sv)) * x0) + S.delta * sv);
+    const cx<TW> ds = realify(P, cvt<TW>(as + al4 * (qk * sv + (2.0 * redot(x0, sv)) * x0) + S.delta * sv));
     const cx<double> dv = cvt<double>(ds);
     stc<TW>(so, g, ss);
     stc<TW>(dout, g, ds);
@@ -287,10 +317,10 @@ struct OOps {
   __device__ __forceinline__ void metrics1(const In&, cx<double> y, Acc1& a) const { a.ny += abs2(y); }
   __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c, double,
                                          AccF& a) const {
-    const cx<double> y = c * in.y;
+    const cx<double> y = realify(P, c * in.y);
     const double q = abs2(y);
     const cx<double> ay = 2.0 * (c * kin + vg * y);
-    const cx<double> gy = ay + (4.0 * P.alpha * q) * y;
+    const cx<double> gy = realify(P, ay + (4.0 * P.alpha * q) * y);
     stc<double>(xk, g, y);
     stc<double>(gk, g, gy);
     stc<TW>(P.s[0], g, cx<TW>{0, 0});
@@ -342,8 +372,8 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   for (int e = 0; e < E; ++e) {
     const cx<double> y = ops.trial(in[e]);
     if constexpr (ROLE == R_FIRST || ROLE == R_SOLO)
-      if (T.act) ops.metrics1(in[e], y, a1);
-    v[e] = cvt<CT>(y);
+      if (T.inner(e)) ops.metrics1(in[e], y, a1);
+    v[e] = cvt<CT>(T.sgn(e) * y);
   }
   if constexpr (ROLE == R_SOLO) {
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
@@ -361,9 +391,9 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   }
   spectral_apply<N, CT>(P, ax, T, v, lds);
   if constexpr (ROLE == R_FIRST) {
-    if (T.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) stc<CT>(P.t, T.g(e), v[e]);
+    for (int e = 0; e < E; ++e)
+      if (T.inner(e)) stc<CT>(P.t, T.g(e), v[e]);
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
     block_reduce<2, 1>(acc, red);
     if (threadIdx.x == 0) {
@@ -373,14 +403,14 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
       gst<double>(P.part1, o + S1_RMAX, acc[2]);
     }
   } else if constexpr (ROLE == R_MID) {
-    if (T.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) stc<CT>(P.t, T.g(e), tv[e] + v[e]);
+    for (int e = 0; e < E; ++e)
+      if (T.inner(e)) stc<CT>(P.t, T.g(e), tv[e] + v[e]);
   } else {
     AccF af;
-    if (T.act)
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < E; ++e)
+      if (T.inner(e)) {
         cx<double> kin = cvt<double>(v[e]);
         if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
         ops.final_(in[e], T.g(e), T.pot_value(P, vp[e]), kin, c, n_hat, af);
@@ -437,10 +467,12 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, 
 // entry.
 __device__ __forceinline__ void pin_desc_fields(ProbDev& P) {
   pin_reg(P.dim); pin_reg(P.n[0]); pin_reg(P.n[1]); pin_reg(P.n[2]);
+  pin_reg(P.nl[0]); pin_reg(P.nl[1]); pin_reg(P.nl[2]); pin_reg(P.bc);
+  pin_reg(P.x0[0]); pin_reg(P.x0[1]);
   pin_reg(P.stride[1]); pin_reg(P.stride[2]); pin_reg(P.m);
   pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
-  pin_reg(P.has_v); pin_reg(P.step_at);
-  pin_reg(P.lo[0]); pin_reg(P.lo[1]); pin_reg(P.h[0]); pin_reg(P.h[1]);
+  pin_reg(P.has_v); pin_reg(P.step_at); pin_reg(P.real);
+  pin_reg(P.h[0]); pin_reg(P.h[1]);
   pin_reg(P.len[0]); pin_reg(P.len[1]); pin_reg(P.len[2]);
   pin_reg(P.omega); pin_reg(P.alpha);
   pin_reg(P.v_arr); pin_reg(P.v_axis);
@@ -485,7 +517,7 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   SolverState S = states[bm.x];
   GPE_PASS_STATE_FIELDS(pin_reg);
   if (S.mode == M_IDLE) return;
-  const int n = pick3(P.n, role_axis(ROLE, P.dim));
+  const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   switch (n) {
     case 16: solver_dispatch<16, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
     case 32: solver_dispatch<32, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;

@@ -39,7 +39,8 @@ def _bound(p, phi, prec):
     mult = sum(0.5 * l * l + rot * l for l in lam)
     vmax = float(np.max(disc.potential(p)))
     amax = float(np.max(np.abs(phi)))
-    lg = max(math.log2(n) for n in p.n)
+    # transform length: n (Fourier) or the 2n-point odd extension (sine)
+    lg = max(math.log2(2 * n if p.bc == W.SINE else n) for n in p.n)
     return CFAC[prec] * EPS[prec] * lg * (mult + vmax + p.beta * amax ** 2) * amax
 
 
@@ -158,3 +159,80 @@ def test_prolong_matches_oracle(dev, dims):
     ref = prolong_fourier(u)
     n = max(dims)
     assert float(np.max(np.abs(got - ref))) < 1e-13 * n * float(np.max(np.abs(ref)))
+
+
+# ---------------------------------------------------------------------------
+# Sine pseudospectral (Dirichlet, DST-I) operator, §2.2: n intervals, n-1
+# interior points per axis.  The oracle's sine path is real (Omega = 0); real
+# data go to the GPU as complex with a zero imaginary part.
+# ---------------------------------------------------------------------------
+SINE_CASES = [
+    W.Problem(dim=1, n=(16,), lo=(-4.0,), hi=(4.0,), bc=W.SINE, beta=10.0),
+    W.Problem(dim=1, n=(512,), lo=(-16.0,), hi=(16.0,), bc=W.SINE, beta=400.0, lattice_amp=20.0),
+    W.Problem(dim=2, n=(32, 64), lo=(-6.0, -8.0), hi=(6.0, 8.0), bc=W.SINE, beta=50.0,
+              gamma=(1.0, 1.5, 1.0)),
+    W.Problem(dim=2, n=(256, 256), lo=(-16.0, -16.0), hi=(16.0, 16.0), bc=W.SINE, beta=500.0,
+              lattice_amp=50.0),
+    W.Problem(dim=3, n=(16, 32, 16), lo=(-5.0, -6.0, -4.0), hi=(5.0, 6.0, 4.0), bc=W.SINE, beta=100.0),
+    W.Problem(dim=3, n=(128, 128, 128), lo=(-8.0,) * 3, hi=(8.0,) * 3, bc=W.SINE, beta=200.0),
+]
+
+
+def _real_field(p, seed):
+    rng = np.random.default_rng(seed)
+    cs = disc.grid_coords(p)
+    r2 = sum(c * c for c in cs)
+    phi = np.exp(-r2 / 4.0) * (1 + 0.3 * cs[0]) + 0.05 * rng.standard_normal(p.shape)
+    return phi / math.sqrt(disc.h_vol(p) * float(np.sum(phi * phi)))
+
+
+def _scid(p):
+    return f"sine-d{p.dim}-" + "x".join(str(n) for n in p.n)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("p", SINE_CASES, ids=_scid)
+def test_apply_h_sine_matches_oracle(dev, p, prec):
+    phi = _real_field(p, 4)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    t = torch.from_numpy(phi.astype(np.complex128)).to(dt).cuda()
+    out, sc = dev.apply_h(p, t, precision=prec)
+    got = out.cpu().numpy().astype(np.complex128)
+    phi_in = t.cpu().numpy().real.astype(np.float64)
+    ref = disc.h_full(p, phi_in)
+    tol = _bound(p, phi_in, prec)
+    assert float(np.max(np.abs(got.real - ref))) <= tol
+    assert float(np.max(np.abs(got.imag))) <= tol                # real data stay real
+    up = UnifiedProblem(p)
+    o = up.outputs(up.to_x(phi_in))
+    rtol = 1e-11 if prec == "fp64" else 3e-6
+    assert abs(sc["energy"] - o["energy"]) <= rtol * abs(o["energy"])
+    assert abs(sc["mu"] - o["mu"]) <= rtol * abs(o["mu"])
+    assert abs(sc["norm2"] - up.hvol * float(np.sum(phi_in ** 2))) <= 1e-12
+    assert abs(sc["resid"] - o["resid"]) <= tol + rtol * o["resid"]
+    for a in range(p.dim):
+        assert abs(sc["rms_" + "xyz"[a]] - o["rms"][a]) <= rtol * o["rms"][a] + 1e-14
+
+
+@pytest.mark.parametrize("p", [SINE_CASES[2], SINE_CASES[4]], ids=_scid)
+def test_apply_h_sine_complex_data(dev, p):
+    # the kinetic part is linear: kin(a + ib) = kin(a) + i kin(b)
+    a, b = _real_field(p, 5), _real_field(p, 6)
+    phi = (a + 1j * b) / math.sqrt(2.0)
+    out, _ = dev.apply_h(p, torch.from_numpy(phi).cuda())
+    kin = disc.kinetic(p, phi.real) + 1j * disc.kinetic(p, phi.imag)
+    ref = kin + disc.potential(p) * phi + p.beta * np.abs(phi) ** 2 * phi
+    assert float(np.max(np.abs(out.cpu().numpy() - ref))) <= _bound(p, phi, "fp64")
+
+
+def test_apply_h_sine_eigenfunction(dev):
+    # beta = 0, V = 0: sin(l pi j / N) x sin(m pi k / N) is an eigenvector of
+    # the sine operator with eigenvalue (lambda_l^2 + lambda_m^2) / 2
+    p = W.Problem(dim=2, n=(64, 32), lo=(0.0, -1.0), hi=(4.0, 3.0), bc=W.SINE, gamma=(0.0, 0.0, 0.0))
+    j = np.arange(1, 64)[None, :]
+    k = np.arange(1, 32)[:, None]
+    l, m = 5, 3
+    f = np.sin(l * np.pi * j / 64) * np.sin(m * np.pi * k / 32) + 0j
+    out, _ = dev.apply_h(p, torch.from_numpy(f).cuda())
+    lam = 0.5 * ((np.pi * l / 4.0) ** 2 + (np.pi * m / 4.0) ** 2)
+    assert float(np.max(np.abs(out.cpu().numpy() - lam * f))) < 1e-12 * lam

@@ -176,3 +176,73 @@ def test_step_placements_agree(dev, case):
         for k in ("nfe", "nfe_fp64", "outer_iters", "inner_iters", "backtracks", "rejections"):
             assert r[k] == r_ref[k], (kw, k, r[k], r_ref[k])
         assert np.array_equal(phi, phi_ref), kw
+
+
+
+@pytest.mark.parametrize("case", ["sine-1d", "sine-2d-lattice", "sine-3d"])
+def test_sine_ground_state(dev, case):
+    # Dirichlet (sine pseudospectral) ground states, real initial data; the
+    # oracle runs the same algorithm in real arithmetic
+    if case == "sine-1d":
+        p = W.Problem(dim=1, n=(128,), lo=(-16.0,), hi=(16.0,), bc=W.SINE, beta=400.0)
+        phi0, tol = W.gaussian_times_noise(p, 0.05, 1), 1e-8
+    elif case == "sine-2d-lattice":
+        p = W.Problem(dim=2, n=(64, 64), lo=(-16.0, -16.0), hi=(16.0, 16.0), bc=W.SINE, beta=500.0,
+                      lattice_amp=50.0)
+        phi0, tol = W.gaussian_times_noise(p, 0.01, 7), 1e-8
+    else:
+        p = W.Problem(dim=3, n=(32, 32, 32), lo=(-8.0,) * 3, hi=(8.0,) * 3, bc=W.SINE, beta=200.0,
+                      lattice_amp=25.0)
+        phi0, tol = W.gaussian_times_noise(p, 0.01, 3), 1e-7
+    up = UnifiedProblem(p)
+    ref = regularized_newton(up, up.to_x(phi0), Options(tol=tol))
+    assert ref.converged
+    for prec in ("fp64", "mixed"):
+        # real phi_0 and Omega = 0: real arithmetic is chosen automatically
+        phi, res = _gpu_solve(dev, p, phi0.astype(np.complex128), tol=tol, precision=prec)
+        assert res["status"] == 0, (prec, res)
+        assert np.all(phi.imag == 0.0), prec
+        _compare(p, phi.real, ref.x, tol, 1e-10, 1e-6)
+
+
+def test_sine_rejections(dev):
+    from paper_1504_02891_amd.api import GpeError
+    p = W.Problem(dim=2, n=(32, 32), lo=(-4.0, -4.0), hi=(4.0, 4.0), bc=W.SINE, omega=0.3)
+    z = torch.ones(31 * 31, dtype=torch.complex128, device="cuda")
+    with pytest.raises(GpeError) as e:
+        dev.solve(p, z)                                            # rotation needs Fourier
+    assert e.value.status == -1
+    q = W.Problem(dim=1, n=(1024,), lo=(-4.0,), hi=(4.0,), bc=W.SINE)
+    with pytest.raises(GpeError) as e:
+        dev.apply_h(q, torch.ones(1023, dtype=torch.complex128, device="cuda"))
+    assert e.value.status == -2                                    # 2n-point extension > 1024
+    with pytest.raises(ValueError):
+        dev.apply_h(W.Problem(dim=1, n=(64,), lo=(-4.0,), hi=(4.0,), bc=W.SINE),
+                    torch.ones(64, dtype=torch.complex128, device="cuda"))   # needs 63 values
+
+
+
+def test_real_field_option(dev):
+    from paper_1504_02891_amd.api import GpeError
+    p, phi0 = W.harmonic_1d(beta=400.0)
+    up = UnifiedProblem(p)
+    ref = regularized_newton(up, up.to_x(phi0), Options(tol=1e-8))
+    # complex phi_0 (a global phase) with Omega = 0: complex arithmetic; the
+    # result is the ground state times a phase
+    phi, res = _gpu_solve(dev, p, phi0 * np.exp(0.3j), tol=1e-8)
+    assert res["status"] == 0
+    assert float(np.max(np.abs(phi.imag))) > 1e-3
+    _compare(p, phi, ref.x, 1e-8, 1e-10, 1e-6)
+    # forced real arithmetic drops the phase's imaginary part at the start
+    phi, res = _gpu_solve(dev, p, phi0 + 0j, tol=1e-8, real_field=1, precision="mixed")
+    assert res["status"] == 0 and np.all(phi.imag == 0.0)
+    _compare(p, phi.real, ref.x, 1e-8, 1e-10, 1e-6)
+    # complex arithmetic on real data still works (rounding may rotate the phase)
+    phi, res = _gpu_solve(dev, p, phi0 + 0j, tol=1e-8, real_field=0)
+    assert res["status"] == 0
+    _compare(p, phi, ref.x, 1e-8, 1e-10, 1e-6)
+    # real arithmetic needs Omega = 0
+    q = W.Problem(dim=2, n=(32, 32), lo=(-6.0, -6.0), hi=(6.0, 6.0), beta=100.0, omega=0.2)
+    with pytest.raises(GpeError) as e:
+        dev.solve(q, torch.from_numpy(W.rotating_initial(q, 0.2, 1)).cuda(), real_field=1)
+    assert e.value.status == -1
