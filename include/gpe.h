@@ -55,6 +55,19 @@ extern "C" {
 #define GPE_ALG1             1   /* Algorithm 1 alone (§3.1) */
 #define GPE_ALG2             2   /* Algorithm 2: K_init steps of Algorithm 1, then regularized Newton (§3.2) */
 
+/* Stop rules (§4).  Norms of X = sqrt(h_vol) phi, the iterate on the unit sphere.
+   RESID: the residual ||H(phi)phi - mu phi||_inf < tol (tested at every iterate).
+   CRIT1: ||X^{k+1} - X^k||_inf / tau_k <= eps0 after an accepted step of Algorithm 1
+          (run alone, or in the first k_init steps of Algorithm 2; the Newton loop
+          then uses RESID).
+   CRIT2: ||X^{k+1} - X^k||_inf <= crit2_tol after an accepted Newton step of
+          Algorithm 2 (the first k_init steps use RESID), or after an accepted step
+          of Algorithm 1 run alone.  A rejected Newton step leaves X unchanged and
+          is not tested. */
+#define GPE_STOP_RESID       0
+#define GPE_STOP_CRIT1       1
+#define GPE_STOP_CRIT2       2
+
 /* Placement of the scalar step (line search / trust-region update) that
    follows each evaluation; results do not depend on it. */
 #define GPE_STEP_AUTO       -1   /* LAST_GROUP when the final pass has at most 128 workgroups
@@ -83,7 +96,7 @@ typedef struct gpe_problem {
 typedef struct gpe_options {
     int32_t precision;    /* GPE_PREC_FP64 or GPE_PREC_MIXED */
     int32_t algorithm;    /* GPE_ALG1 or GPE_ALG2 */
-    double tol;           /* stop when ||H(phi)phi - mu phi||_inf < tol (phi units) */
+    double tol;           /* GPE_STOP_RESID: stop when ||H(phi)phi - mu phi||_inf < tol (phi units) */
     int32_t k_init;       /* Algorithm 1 steps before the Newton loop (100, §4.3) */
     int32_t k_sub;        /* max Algorithm 1 steps per Newton subproblem (200, §4.3) */
     int32_t max_outer;    /* max Newton steps */
@@ -107,6 +120,10 @@ typedef struct gpe_options {
     int32_t threads[3];   /* workgroup size of the x, y, z passes (0 = built-in choice);
                              a multiple of 64 and of n/8, at most 256 */
     int32_t step_at;      /* where the scalar step of the solver runs (GPE_STEP_*) */
+    int32_t stop_rule;    /* GPE_STOP_RESID (default), GPE_STOP_CRIT1 or GPE_STOP_CRIT2 */
+    int32_t monotone;     /* 1: monotone Armijo search, C = F(X_k) (eta = 0); 0: Zhang-Hager */
+    double eps0;          /* GPE_STOP_CRIT1 threshold (1e-6, §4) */
+    double crit2_tol;     /* GPE_STOP_CRIT2 threshold delta_0 (1e-8, §4) */
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */

@@ -62,6 +62,15 @@ class Options:
     delta0: float = 1.0
     delta_min: float = 1e-12
     delta_max: float = 1e12
+    # stop rule: "resid" (r < tol), or the paper's step-length rules (§4):
+    # "crit1" ||X^{k+1} - X^k||_inf / tau_k <= eps0 on the steps of
+    # Algorithm 1 (alone, and in the first K_init steps of Algorithm 2);
+    # "crit2" ||X^{k+1} - X^k||_inf <= crit2_tol on accepted Newton steps of
+    # Algorithm 2 (and on the steps of Algorithm 1 run alone).  Norms in X units.
+    stop_rule: str = "resid"
+    eps0: float = 1e-6
+    crit2_tol: float = 1e-8
+    monotone: bool = False      # monotone Armijo (C = F(X_k)) instead of Zhang-Hager
 
 
 @dataclasses.dataclass
@@ -77,8 +86,24 @@ class SolveResult:
 
 
 def _fg_kwargs(o):
-    return dict(rho1=o.rho1, eta=o.eta, sigma=o.sigma, m_max=o.m_max,
+    return dict(rho1=o.rho1, eta=0.0 if o.monotone else o.eta, sigma=o.sigma, m_max=o.m_max,
                 renorm_tol=o.renorm_tol)
+
+
+def _inf_norm(d):
+    return float(np.max(np.abs(d)))
+
+
+def _alg1_stops(up, o):
+    """(stop, stop_step) of Algorithm 1 on F under the configured rule."""
+    never = lambda *a: False
+    if o.stop_rule == "resid":
+        return (lambda x_, f_, g_, P_: up.residual(x_, g_) < o.tol), None
+    if o.stop_rule == "crit1":
+        return never, (lambda xn, xo, t: _inf_norm(xn - xo) / t <= o.eps0)
+    if o.stop_rule == "crit2":
+        return never, (lambda xn, xo, t: _inf_norm(xn - xo) <= o.crit2_tol)
+    raise ValueError(f"unknown stop rule {o.stop_rule}")
 
 
 def feasible_only(up, x0, opts: Options):
@@ -87,9 +112,9 @@ def feasible_only(up, x0, opts: Options):
     st = FGStats()
     f, g = up.f_and_grad(x)
     st.nfe += 1
+    stop, stop_step = _alg1_stops(up, opts)
     res = feasible_gradient(up.f_and_grad, x, f, g, maxit=opts.max_iter_alg1,
-                            tau_init=opts.tau0,
-                            stop=lambda x_, f_, g_, P_: up.residual(x_, g_) < opts.tol,
+                            tau_init=opts.tau0, stop=stop, stop_step=stop_step,
                             stats=st, **_fg_kwargs(opts))
     return SolveResult(res.x, res.stopped, 0, st.iters, st.nfe, st.backtracks)
 
@@ -101,20 +126,31 @@ def regularized_newton(up, x0, opts: Options, log=False):
     st = FGStats()
     f, g = up.f_and_grad(x)
     st.nfe += 1
+    # the K_init steps of Algorithm 1: residual rule, or crit1 (crit2 is a
+    # rule of the outer loop)
+    if o.stop_rule == "crit1":
+        stop, stop_step = _alg1_stops(up, o)
+    else:
+        stop, stop_step = (lambda x_, f_, g_, P_: up.residual(x_, g_) < o.tol), None
     res = feasible_gradient(up.f_and_grad, x, f, g, maxit=o.k_init, tau_init=o.tau0,
-                            stop=lambda x_, f_, g_, P_: up.residual(x_, g_) < o.tol,
-                            stats=st, **_fg_kwargs(o))
+                            stop=stop, stop_step=stop_step, stats=st, **_fg_kwargs(o))
     x, tau = res.x, res.tau_bb
     delta = o.delta0
     out = SolveResult(x, False)
     alpha = up.alpha
+    x_prev = None                # previous outer iterate when the last step was accepted
     for outer in range(o.max_outer + 1):
         f, g = up.f_and_grad(x)                  # outer evaluation at X_k
         st.nfe += 1
         r = up.residual(x, g)
         if log:
             out.log.append((outer, f, r, delta))
-        if r < o.tol:
+        if o.stop_rule == "crit2":
+            # a rejected step leaves X unchanged and is not a step (reading)
+            if x_prev is not None and _inf_norm(x - x_prev) <= o.crit2_tol:
+                out.converged = True
+                break
+        elif r < o.tol:
             out.converged = True
             break
         if outer == o.max_outer:
@@ -146,8 +182,10 @@ def regularized_newton(up, x0, opts: Options, log=False):
                                        * (np.abs(z) ** 2 + qk))))
         rho = ared / pred if pred < 0.0 else -math.inf
         if rho >= o.eta1:
+            x_prev = x
             x = z / math.sqrt(re_dot(z, z))
         else:
+            x_prev = None
             out.rejections += 1
         if rho > o.eta2:
             delta *= o.gamma_shrink

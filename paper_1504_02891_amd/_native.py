@@ -27,6 +27,9 @@ GPE_ALG2 = 2
 GPE_STEP_AUTO = -1
 GPE_STEP_LAST_GROUP = 0
 GPE_STEP_KERNEL = 1
+GPE_STOP_RESID = 0
+GPE_STOP_CRIT1 = 1
+GPE_STOP_CRIT2 = 2
 
 EXPORTS = ("gpe_ctx_create", "gpe_ctx_destroy", "gpe_options_default", "gpe_strerror",
            "gpe_last_error", "gpe_apply_h", "gpe_hess_vec", "gpe_retract", "gpe_solve",
@@ -50,7 +53,9 @@ class Options(C.Structure):
                 ("gamma_grow", C.c_double),
                 ("delta0", C.c_double), ("delta_min", C.c_double), ("delta_max", C.c_double),
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
-                ("real_field", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32)]
+                ("real_field", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32),
+                ("stop_rule", C.c_int32), ("monotone", C.c_int32), ("eps0", C.c_double),
+                ("crit2_tol", C.c_double)]
 
 
 class Result(C.Structure):

@@ -77,6 +77,10 @@ def options(**kw):
     alg = kw.pop("algorithm", None)
     if alg is not None:
         o.algorithm = {"alg1": N.GPE_ALG1, "alg2": N.GPE_ALG2}.get(alg, alg)
+    rule = kw.pop("stop_rule", None)
+    if rule is not None:
+        o.stop_rule = {"resid": N.GPE_STOP_RESID, "crit1": N.GPE_STOP_CRIT1,
+                       "crit2": N.GPE_STOP_CRIT2}.get(rule, rule)
     step = kw.pop("step_at", None)
     if step is not None:
         o.step_at = {"auto": N.GPE_STEP_AUTO, "last_group": N.GPE_STEP_LAST_GROUP,

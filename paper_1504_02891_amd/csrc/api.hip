@@ -237,6 +237,10 @@ void set_default(gpe_options* o) {
   o->real_field = -1;
   o->threads[0] = o->threads[1] = o->threads[2] = 0;
   o->step_at = GPE_STEP_AUTO;
+  o->stop_rule = GPE_STOP_RESID;
+  o->monotone = 0;
+  o->eps0 = 1e-6;
+  o->crit2_tol = 1e-8;
 }
 
 // ---------------------------------------------------------------------------
@@ -312,7 +316,9 @@ void init_state(SolverState& S, const gpe_options& o) {
   S.p = 1.0; S.q = 0.0; S.pm1 = 0.0;
   S.a_b = 0.0; S.n_b = 1.0; S.ng_b = 0.0;
   S.delta = o.delta0;
-  S.tol = o.tol; S.tau0 = o.tau0; S.rho1 = o.rho1; S.eta = o.eta; S.sigma = o.sigma;
+  S.tol = o.tol; S.tau0 = o.tau0; S.rho1 = o.rho1; S.sigma = o.sigma;
+  S.eta = o.monotone ? 0.0 : o.eta;      // monotone Armijo: C = F(X_k)
+  S.stop_rule = o.stop_rule; S.eps0 = o.eps0; S.crit2_tol = o.crit2_tol;
   S.renorm_tol = o.renorm_tol;
   S.eta1 = o.eta1; S.eta2 = o.eta2; S.gshrink = o.gamma_shrink; S.ggrow = o.gamma_grow;
   S.delta_min = o.delta_min; S.delta_max = o.delta_max;
@@ -331,6 +337,9 @@ int check_options(const gpe_options* o) {
   if (o->chunk < 1 || o->chunk > 4096) return GPE_EINVAL;
   if (o->step_at < GPE_STEP_AUTO || o->step_at > GPE_STEP_KERNEL) return GPE_EINVAL;
   if (o->real_field < -1 || o->real_field > 1) return GPE_EINVAL;
+  if (o->stop_rule < GPE_STOP_RESID || o->stop_rule > GPE_STOP_CRIT2) return GPE_EINVAL;
+  if (o->monotone != 0 && o->monotone != 1) return GPE_EINVAL;
+  if (!(o->eps0 >= 0.0) || !(o->crit2_tol >= 0.0)) return GPE_EINVAL;
   return GPE_OK;
 }
 

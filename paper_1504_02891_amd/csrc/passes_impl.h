@@ -299,7 +299,7 @@ struct WOps {
 // Float64 evaluation at a new outer iterate; writes X_k, G_k and clears S/D.
 template <typename TF, typename TW>
 struct OOps {
-  struct In { cx<double> y; };
+  struct In { cx<double> y, x0; };     // the point before renormalisation, and the old X_k
   const ProbDev& P; const SolverState& S;
   void *xk, *gk; const void *xf, *sc;
   __device__ OOps(const ProbDev& P_, const SolverState& S_) : P(P_), S(S_) {
@@ -309,9 +309,13 @@ struct OOps {
     sc = sel2(P.s, S.cur);
   }
   __device__ __forceinline__ In load(int64_t g) const {
-    if (S.src == SRC_XF) return In{cvt<double>(ld<TF>(xf, g))};
-    if (S.src == SRC_XK_PLUS_S) return In{ld<double>(xk, g) + cvt<double>(ld<TW>(sc, g))};
-    return In{ld<double>(xk, g)};
+    if (S.src == SRC_XF) {
+      const cx<double> y = cvt<double>(ld<TF>(xf, g));
+      return In{y, y};
+    }
+    const cx<double> x0 = ld<double>(xk, g);
+    if (S.src == SRC_XK_PLUS_S) return In{x0 + cvt<double>(ld<TW>(sc, g)), x0};
+    return In{x0, x0};
   }
   __device__ __forceinline__ cx<double> trial(const In& in) const { return in.y; }
   __device__ __forceinline__ void metrics1(const In&, cx<double> y, Acc1& a) const { a.ny += abs2(y); }
@@ -329,6 +333,7 @@ struct OOps {
     a.s[SF_A] += redot(y, gy);
     a.s[SF_NG] += abs2(gy);
     a.s[SF_NY] += q;
+    a.smax = fmax(a.smax, abs2(y - in.x0));      // |X_{k+1} - X_k|^2 (Newton step lengths)
   }
 };
 

@@ -89,6 +89,11 @@ __device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, con
     return;
   }
   if (S.phase == PH_OUTER) {
+    // crit2 on an accepted Newton step: max |X_{k+1} - X_k| from this evaluation
+    if (S.stop_rule == STOP_CRIT2 && S.src == SRC_XK_PLUS_S && sqrt(rf[SF_SMAX]) <= S.crit2_tol) {
+      finish(S, 0, SRC_XK);
+      return;
+    }
     S.f_outer = rf[SF_F];
     S.a_b = rf[SF_A]; S.n_b = rf[SF_NY]; S.ng_b = rf[SF_NG]; S.f_b = 0.0;
     S.k = 0; S.m = 0; S.C = 0.0; S.Q = 1.0;
@@ -106,11 +111,12 @@ __device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, con
     S.np2_b = r1[S1_NP2];
     const double rb = sqrt(r1[S1_RMAX]) * rscale;   // residual of the base point (phi units)
     if (S.phase == PH_ALG1) {
-      if (rb < S.tol) { end_alg1(S, true); return; }
+      const bool resid_rule = S.stop_rule == STOP_RESID || (S.alg == 2 && S.stop_rule == STOP_CRIT2);
+      if (resid_rule && rb < S.tol) { end_alg1(S, true); return; }
     } else {
       if (S.k == 0) {
         S.r_outer = rb;
-        if (rb < S.tol) { finish(S, 0, SRC_XK); return; }
+        if (S.stop_rule != STOP_CRIT2 && rb < S.tol) { finish(S, 0, SRC_XK); return; }
         if (S.outer >= S.max_outer) { finish(S, 1, SRC_XK); return; }
         const double npk = sqrt(S.np2_b);
         S.forcing = fmin(0.1, npk) * npk;
@@ -133,6 +139,15 @@ __device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, con
     S.C = (S.eta * S.Q * S.C + S.f_b) / qn;
     S.Q = qn;
     S.k++; S.inner_total++; S.m = 0;
+    if (S.phase == PH_ALG1 &&
+        (S.stop_rule == STOP_CRIT1 || (S.alg == 1 && S.stop_rule == STOP_CRIT2))) {
+      // step-length rules on the accepted step of length t (max |S_j|^2 of this trial)
+      const double dx = sqrt(rf[SF_SMAX]);
+      if (S.stop_rule == STOP_CRIT1 ? dx <= S.eps0 * S.t : dx <= S.crit2_tol) {
+        end_alg1(S, true);
+        return;
+      }
+    }
     if (S.k >= S.maxit) {
       if (S.phase == PH_ALG1) end_alg1(S, false);
       else end_inner(S);

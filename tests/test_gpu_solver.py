@@ -246,3 +246,57 @@ def test_real_field_option(dev):
     with pytest.raises(GpeError) as e:
         dev.solve(q, torch.from_numpy(W.rotating_initial(q, 0.2, 1)).cuda(), real_field=1)
     assert e.value.status == -1
+
+
+def test_stop_rule_crit1_sine_1d(dev):
+    # §4.1: Algorithm 1 on the sine discretization, crit1 with eps0 = 1e-12,
+    # reproduces the printed values; the oracle runs the same rule
+    gold = {"energy": 21.3601, "mu": 35.5775, "x_rms": 3.7751}
+    p = W.Problem(dim=1, n=(256,), lo=(-16.0,), hi=(16.0,), bc=W.SINE, beta=400.0)
+    xs = disc.axis_points(p, 0)
+    f0 = np.exp(-xs * xs / 2) + 0j
+    up = UnifiedProblem(p)
+    ref = feasible_only(up, up.to_x(f0.real), Options(stop_rule="crit1", eps0=1e-12))
+    assert ref.converged
+    phi, res = _gpu_solve(dev, p, f0, algorithm="alg1", stop_rule="crit1", eps0=1e-12, tol=0.0)
+    assert res["status"] == 0, res
+    assert round(res["energy"], 4) == gold["energy"] and round(res["mu"], 4) == gold["mu"]
+    assert round(res["rms"][0], 4) == gold["x_rms"]
+    _compare(p, phi.real, ref.x, 1e-9, 1e-12, 1e-8)
+    assert abs(res["inner_iters"] - ref.inner) <= 0.25 * ref.inner, (res["inner_iters"], ref.inner)
+    # eps0 = inf: the first accepted step stops Algorithm 1
+    for prec in ("fp64", "mixed"):
+        _, r1 = _gpu_solve(dev, p, f0, algorithm="alg1", stop_rule="crit1", eps0=math.inf, precision=prec)
+        assert r1["status"] == 0 and r1["inner_iters"] == 1, (prec, r1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_stop_rule_crit2_newton(dev, prec):
+    # Algorithm 2 stopped by crit2 on accepted Newton steps
+    p = W.Problem(dim=2, n=(64, 64), lo=(-10.0, -10.0), hi=(10.0, 10.0), beta=500.0, omega=0.25)
+    phi0 = W.rotating_initial(p, 0.25, 2)
+    up = UnifiedProblem(p)
+    ref = regularized_newton(up, up.to_x(phi0), Options(stop_rule="crit2", crit2_tol=1e-8))
+    assert ref.converged
+    phi, res = _gpu_solve(dev, p, phi0, stop_rule="crit2", crit2_tol=1e-8, precision=prec)
+    assert res["status"] == 0, res
+    # the step rule bounds the step, not the residual: compare energies, and
+    # the state loosely (the oracle's residual at its own stop is the scale)
+    og = up.outputs(ref.x)
+    assert abs(res["energy"] - og["energy"]) <= 1e-9 * og["energy"]
+    assert res["resid"] < 100 * max(og["resid"], 1e-7)
+    # crit2_tol = inf: the evaluation after the first accepted Newton step stops
+    _, r2 = _gpu_solve(dev, p, phi0, stop_rule="crit2", crit2_tol=math.inf, precision=prec)
+    assert r2["status"] == 0 and r2["outer_iters"] == r2["rejections"] + 1, r2
+
+
+def test_monotone_search(dev):
+    # monotone Armijo (eta = 0) on the GPU follows the oracle's monotone run
+    p, phi0 = W.harmonic_1d(beta=400.0)
+    up = UnifiedProblem(p)
+    ref = feasible_only(up, up.to_x(phi0), Options(tol=1e-8, monotone=True))
+    assert ref.converged
+    phi, res = _gpu_solve(dev, p, phi0 + 0j, algorithm="alg1", monotone=1, tol=1e-8)
+    assert res["status"] == 0, res
+    _compare(p, phi.real, ref.x, 1e-8, 1e-10, 1e-6)
+    assert abs(res["inner_iters"] - ref.inner) <= 0.25 * ref.inner, (res["inner_iters"], ref.inner)
