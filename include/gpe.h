@@ -124,6 +124,10 @@ typedef struct gpe_options {
     int32_t monotone;     /* 1: monotone Armijo search, C = F(X_k) (eta = 0); 0: Zhang-Hager */
     double eps0;          /* GPE_STOP_CRIT1 threshold (1e-6, §4) */
     double crit2_tol;     /* GPE_STOP_CRIT2 threshold delta_0 (1e-8, §4) */
+    int32_t switch_window;/* mixed precision, Algorithm 1: when the residual has not halved in
+                             this many accepted steps (the FP32 floor), continue from the current
+                             iterate in FP64 with the remaining steps; 0 = never (default 100) */
+    int32_t reserved1;
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */
@@ -135,7 +139,8 @@ typedef struct gpe_result {
     int32_t nfe_fp64;     /* of which evaluated in float64 */
     int32_t backtracks;   /* step-size reductions */
     int32_t rejections;   /* rejected Newton trial points */
-    int32_t reserved;
+    int32_t switch_iter;  /* mixed precision, Algorithm 1: steps taken in FP32 before the
+                             FP64 continuation (0 = no switch) */
     double energy;        /* E_h(phi)  (§2) */
     double mu;            /* E + beta/2 int |phi|^4  (§1) */
     double resid;         /* ||H(phi)phi - mu phi||_inf */

@@ -55,13 +55,13 @@ class Options(C.Structure):
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
                 ("real_field", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32),
                 ("stop_rule", C.c_int32), ("monotone", C.c_int32), ("eps0", C.c_double),
-                ("crit2_tol", C.c_double)]
+                ("crit2_tol", C.c_double), ("switch_window", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer_iters", C.c_int32), ("inner_iters", C.c_int32),
                 ("nfe", C.c_int32), ("nfe_fp64", C.c_int32), ("backtracks", C.c_int32),
-                ("rejections", C.c_int32), ("reserved", C.c_int32),
+                ("rejections", C.c_int32), ("switch_iter", C.c_int32),
                 ("energy", C.c_double), ("mu", C.c_double), ("resid", C.c_double),
                 ("norm_err", C.c_double), ("rms", C.c_double * 3), ("max_dens", C.c_double),
                 ("delta", C.c_double), ("time_ms", C.c_double),
@@ -69,7 +69,7 @@ class Result(C.Structure):
                 ("pass_launches", C.c_int32), ("pass_ms", C.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("rms", "reserved")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "rms"}
         d["rms"] = list(self.rms)
         return d
 

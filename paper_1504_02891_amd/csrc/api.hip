@@ -241,6 +241,8 @@ void set_default(gpe_options* o) {
   o->monotone = 0;
   o->eps0 = 1e-6;
   o->crit2_tol = 1e-8;
+  o->switch_window = 100;
+  o->reserved1 = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -319,6 +321,7 @@ void init_state(SolverState& S, const gpe_options& o) {
   S.tol = o.tol; S.tau0 = o.tau0; S.rho1 = o.rho1; S.sigma = o.sigma;
   S.eta = o.monotone ? 0.0 : o.eta;      // monotone Armijo: C = F(X_k)
   S.stop_rule = o.stop_rule; S.eps0 = o.eps0; S.crit2_tol = o.crit2_tol;
+  S.switch_window = o.switch_window; S.since_best = 0; S.best_r = INFINITY;
   S.renorm_tol = o.renorm_tol;
   S.eta1 = o.eta1; S.eta2 = o.eta2; S.gshrink = o.gamma_shrink; S.ggrow = o.gamma_grow;
   S.delta_min = o.delta_min; S.delta_max = o.delta_max;
@@ -339,7 +342,7 @@ int check_options(const gpe_options* o) {
   if (o->real_field < -1 || o->real_field > 1) return GPE_EINVAL;
   if (o->stop_rule < GPE_STOP_RESID || o->stop_rule > GPE_STOP_CRIT2) return GPE_EINVAL;
   if (o->monotone != 0 && o->monotone != 1) return GPE_EINVAL;
-  if (!(o->eps0 >= 0.0) || !(o->crit2_tol >= 0.0)) return GPE_EINVAL;
+  if (!(o->eps0 >= 0.0) || !(o->crit2_tol >= 0.0) || o->switch_window < 0) return GPE_EINVAL;
   return GPE_OK;
 }
 
@@ -643,6 +646,58 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   return worst;
 }
 
+// Solve, then continue in FP64 the problems whose mixed-precision Algorithm 1
+// stalled at the FP32 floor (internal status kStatusStalled): the iterate
+// each left in its phi buffer starts an FP64 run of Algorithm 1 with the
+// remaining step budget.  Counters add up; the outputs are the FP64 run's.
+int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
+                 gpe_result* results) {
+  int rc = solve_impl(c, count, probs, opts, phis, results);
+  if (rc < 0) return rc;
+  std::vector<int> idx;
+  for (int i = 0; i < count; ++i)
+    if (results[i].status == kStatusStalled) idx.push_back(i);
+  if (idx.empty()) return rc;
+  std::vector<gpe_problem> sp;
+  std::vector<void*> sphi;
+  int used = 0;
+  for (int i : idx) {
+    sp.push_back(probs[i]);
+    sphi.push_back(phis[i]);
+    used = std::max(used, results[i].inner_iters);
+  }
+  gpe_options o2 = *opts;
+  o2.precision = GPE_PREC_FP64;
+  o2.max_iter = std::max(0, opts->max_iter - used);
+  std::vector<gpe_result> r2(idx.size());
+  const int rc2 = solve_impl(c, (int)idx.size(), sp.data(), &o2, sphi.data(), r2.data());
+  if (rc2 < 0) return rc2;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    gpe_result& a = results[idx[k]];
+    gpe_result b = r2[k];
+    b.switch_iter = a.inner_iters;
+    b.outer_iters += a.outer_iters;
+    b.inner_iters += a.inner_iters;
+    b.nfe += a.nfe;
+    b.nfe_fp64 += a.nfe_fp64;
+    b.backtracks += a.backtracks;
+    b.rejections += a.rejections;
+    b.nfe_f += a.nfe_f;
+    b.nfe_w += a.nfe_w;
+    b.nfe_outer += a.nfe_outer;
+    b.time_ms += a.time_ms;
+    b.pass_launches += a.pass_launches;
+    b.pass_ms += a.pass_ms;
+    a = b;
+  }
+  int worst = GPE_OK;
+  for (int i = 0; i < count; ++i) {
+    if (results[i].status < 0 && worst >= 0) worst = results[i].status;
+    else if (results[i].status == GPE_NOT_CONVERGED && worst == GPE_OK) worst = GPE_NOT_CONVERGED;
+  }
+  return worst;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -768,12 +823,12 @@ int gpe_retract(gpe_ctx* c, int64_t m, const void* x, const void* g, double tau,
 
 int gpe_solve(gpe_ctx* c, const gpe_problem* prob, const gpe_options* opts, void* phi, gpe_result* result) {
   void* phis[1] = {phi};
-  return solve_impl(c, 1, prob, opts, phis, result);
+  return solve_switch(c, 1, prob, opts, phis, result);
 }
 
 int gpe_solve_batched(gpe_ctx* c, int32_t count, const gpe_problem* probs, const gpe_options* opts,
                       void* const* phis, gpe_result* results) {
-  return solve_impl(c, count, probs, opts, phis, results);
+  return solve_switch(c, count, probs, opts, phis, results);
 }
 
 int gpe_prolong(gpe_ctx* c, const gpe_problem* coarse, const gpe_problem* fine, const void* phi_c, void* phi_f) {
@@ -847,7 +902,7 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
         HIPCHK(hipMemcpyAsync(phis[i], cur[i], m * 16, hipMemcpyDeviceToDevice, c->s));
         CHK(end_call(c));
       }
-    rc = solve_impl(c, count, lev.data(), &o, dst.data(), tmp.data());
+    rc = solve_switch(c, count, lev.data(), &o, dst.data(), tmp.data());
     if (rc < 0) return rc;
     for (int i = 0; i < count; ++i) {
       nfe[i] += tmp[i].nfe; nfe64[i] += tmp[i].nfe_fp64;

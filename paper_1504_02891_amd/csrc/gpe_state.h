@@ -44,6 +44,10 @@ enum Phase : int32_t { PH_INIT = 0, PH_ALG1 = 1, PH_OUTER = 2, PH_INNER = 3, PH_
 // Where the scalar step after an evaluation runs (see the GPE_STEP_* values).
 enum StepAt : int32_t { STEP_LAST_GROUP = 0, STEP_KERNEL = 1 };
 
+// Internal status: mixed-precision Algorithm 1 stalled at the FP32 floor; the
+// host continues in FP64.
+constexpr int kStatusStalled = 2;
+
 // Stop rules (the GPE_STOP_* values).
 enum StopRule : int32_t { STOP_RESID = 0, STOP_CRIT1 = 1, STOP_CRIT2 = 2 };
 
@@ -99,7 +103,7 @@ struct SolverState {
   int32_t k, m, maxit, outer;
   int32_t nfe, nfe64, inner_total, backtracks;
   int32_t rejections, max_outer, nfe_f, nfe_w;
-  int32_t nfe_o, stop_rule, pad2, pad3;
+  int32_t nfe_o, stop_rule, switch_window, since_best;   // since_best: steps without halving best_r
   // trial coefficients of the retraction, Y = p X_b + q g_b (pm1 = p - 1)
   double p, q, pm1, t;
   // scalars of the current base point
@@ -114,6 +118,7 @@ struct SolverState {
   double tol, tau0, rho1, eta, sigma, renorm_tol;
   double eta1, eta2, gshrink, ggrow, delta_min, delta_max;
   double eps0, crit2_tol;                  // thresholds of the step-length stop rules
+  double best_r, pad_d;                    // best residual of Algorithm 1 (stall test)
   int32_t k_init, k_sub, m_max, max_iter;
   int32_t pad4, pad5;                      // whole 16-byte words (read with 16-byte loads)
 };

@@ -113,6 +113,16 @@ __device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, con
     if (S.phase == PH_ALG1) {
       const bool resid_rule = S.stop_rule == STOP_RESID || (S.alg == 2 && S.stop_rule == STOP_CRIT2);
       if (resid_rule && rb < S.tol) { end_alg1(S, true); return; }
+      if (!prec64 && S.alg == 1 && S.switch_window > 0) {
+        // FP32 floor: no halving of the best residual within the window
+        if (rb < 0.5 * S.best_r) {
+          S.best_r = rb;
+          S.since_best = 0;
+        } else if (++S.since_best >= S.switch_window) {
+          finish(S, kStatusStalled, SRC_XF);
+          return;
+        }
+      }
     } else {
       if (S.k == 0) {
         S.r_outer = rb;
