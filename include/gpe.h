@@ -148,7 +148,8 @@ typedef struct gpe_result {
     double rms[3];        /* sqrt(int x_i^2 |phi|^2)  (§4, rms) */
     double max_dens;      /* max |phi|^2 */
     double delta;         /* final regularisation delta */
-    double time_ms;       /* device time of the solve (events on the context stream) */
+    double time_ms;       /* device time of the evaluation loop (events on the context stream;
+                             setup, graph instantiation and the output pass excluded) */
     int32_t nfe_f;        /* evaluations of F in Algorithm 1 (including the initial one) */
     int32_t nfe_w;        /* evaluations of the Newton model W */
     int32_t nfe_outer;    /* float64 evaluations of F at outer iterates */
@@ -224,6 +225,22 @@ int gpe_solve(gpe_ctx* ctx, const gpe_problem* prob, const gpe_options* opts,
  */
 int gpe_solve_batched(gpe_ctx* ctx, int32_t count, const gpe_problem* probs,
                       const gpe_options* opts, void* const* phis, gpe_result* results);
+
+/*
+ * Tuning of the launch configuration for one grid (dim, n, bc) and precision:
+ * short solves of a synthetic state on that grid time every valid workgroup
+ * size per pass (64, 128, 256 threads, a multiple of n/8) and both step
+ * placements; the fastest plan is kept in the context (one per grid and
+ * precision, replaced by a later call).  Later gpe_solve / gpe_solve_batched /
+ * gpe_solve_cascadic calls on a context with a plan for their grid use it
+ * wherever their options leave the choice open (threads 0, step_at AUTO).
+ * A plan changes the tiling, hence the order of the float64 reductions, not
+ * the method.  threads_out[3], step_at_out, us_per_eval_out: HOST, optional
+ * (the chosen plan and its time per evaluation in microseconds).  Takes a few
+ * hundred milliseconds to seconds; allocates device workspace in the context.
+ */
+int gpe_autotune(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, int32_t* threads_out,
+                 int32_t* step_at_out, double* us_per_eval_out);
 
 /*
  * Trigonometric prolongation for the cascadic multigrid (Algorithm 3): the

@@ -185,6 +185,20 @@ def solve_batched(probs, phi0s, **opts):
     return phis, [r.as_dict() for r in res]
 
 
+def autotune(p, precision="mixed", device=0):
+    """Time the launch configurations for the grid of ``p`` and keep the
+    fastest in the device's context; later solves on that grid use it where
+    their options leave the choice open.  Returns the plan."""
+    prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
+    thr = (C.c_int32 * 3)()
+    step = C.c_int32()
+    us = C.c_double()
+    ps = problem_struct(p)
+    _check(N.lib().gpe_autotune(context(device), C.byref(ps), prec, thr, C.byref(step), C.byref(us)),
+           "gpe_autotune")
+    return {"threads": list(thr), "step_at": step.value, "us_per_eval": us.value}
+
+
 def prolong(p_coarse, p_fine, phi_c):
     _dev_tensor(phi_c, torch.complex128, "phi_c", p_coarse)
     shape = tuple(int(n) for n in reversed(p_fine.n[: p_fine.dim]))

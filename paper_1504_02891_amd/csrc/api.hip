@@ -38,13 +38,20 @@ constexpr int kApplyThreads = 128;
 enum WsSlot {
   WS_PROB = 0, WS_STATE, WS_BMAP0, WS_BMAP1, WS_BMAP2, WS_VAXIS, WS_ARENA,
   WS_APPLY_T, WS_APPLY_PART, WS_APPLY_OUT, WS_APPLY_RPART, WS_APPLY_PROB, WS_APPLY_VAXIS,
-  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_IMAG, WS_COUNT
+  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_IMAG, WS_TUNE, WS_COUNT
 };
 
 }  // namespace
 
+// A tuned launch configuration (gpe_autotune) for one grid and precision.
+struct TunedPlan {
+  int dim, bc, n[3], prec;
+  int threads[3], step_at;
+};
+
 struct gpe_ctx {
   int device = 0;
+  std::vector<TunedPlan> plans;
   hipStream_t user = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
@@ -354,11 +361,32 @@ int64_t eval_cap(const gpe_options& o) {
   return (int64_t)(o.k_init + 2) * per + (int64_t)(o.max_outer + 2) * ((int64_t)o.k_sub * per + 4) + 16;
 }
 
+// The context's tuned plan for a grid and precision, or null.
+const TunedPlan* find_plan(const gpe_ctx* c, const gpe_problem& p, int prec) {
+  for (const TunedPlan& t : c->plans) {
+    bool same = t.dim == p.dim && t.bc == p.bc && t.prec == prec;
+    for (int a = 0; a < p.dim && same; ++a) same = t.n[a] == p.n[a];
+    if (same) return &t;
+  }
+  return nullptr;
+}
+
 int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
                gpe_result* results) {
   if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
   CHK(check_options(opts));
-  const gpe_options& o = *opts;
+  gpe_options o = *opts;
+  // a tuned plan applies when every problem has its grid and the options
+  // leave the launch choices open
+  if (const TunedPlan* tp = find_plan(c, probs[0], o.precision)) {
+    bool all = true;
+    for (int i = 1; i < count; ++i) all = all && find_plan(c, probs[i], o.precision) == tp;
+    if (all) {
+      if (o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0)
+        for (int a = 0; a < 3; ++a) o.threads[a] = tp->threads[a];
+      if (o.step_at == GPE_STEP_AUTO) o.step_at = tp->step_at;
+    }
+  }
   const int prec64 = o.precision == GPE_PREC_FP64;
   const size_t es = prec64 ? 16 : 8;       // element size of F / W arrays
   std::vector<ProbDev> pd(count);
@@ -504,7 +532,6 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   }
   const ProbDev* P = (const ProbDev*)dprob;
   SolverState* S = (SolverState*)dstate;
-  HIPCHK(hipEventRecord(c->t0, c->s));
   for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd[i].m, phis[i], prec64);
   HIPCHK(hipGetLastError());
 
@@ -555,6 +582,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   const int64_t cap = eval_cap(o);
   int64_t evals = 0;
   int rc = GPE_OK;
+  HIPCHK(hipEventRecord(c->t0, c->s));
   for (;;) {
     if (exec) {
       if (hipGraphLaunch(exec, c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
@@ -829,6 +857,88 @@ int gpe_solve(gpe_ctx* c, const gpe_problem* prob, const gpe_options* opts, void
 int gpe_solve_batched(gpe_ctx* c, int32_t count, const gpe_problem* probs, const gpe_options* opts,
                       void* const* phis, gpe_result* results) {
   return solve_switch(c, count, probs, opts, phis, results);
+}
+
+int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t* threads_out,
+                 int32_t* step_at_out, double* us_per_eval_out) {
+  if (!c || !prob) return GPE_EINVAL;
+  if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
+  ProbDev d;
+  CHK(build_prob(prob, &d, nullptr));
+  // synthetic state on the grid: a Gaussian (with a vortex-like phase when
+  // rotating, so that the complex path is timed)
+  const size_t m = (size_t)d.m;
+  std::vector<double> h(2 * m);
+  for (size_t g = 0; g < m; ++g) {
+    size_t r = g;
+    double q = 0.0, xy[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d.dim; ++a) {
+      const size_t i = r % (size_t)d.n[a];
+      r /= (size_t)d.n[a];
+      xy[a] = d.x0[a] + d.h[a] * (double)i;
+      q += xy[a] * xy[a];
+    }
+    const double e = std::exp(-0.5 * q);
+    h[2 * g] = e * (1.0 + 0.1 * xy[0]);
+    h[2 * g + 1] = d.omega != 0.0 ? e * 0.1 * xy[1] : 0.0;
+  }
+  void* buf;
+  CHK(ws_get(c, WS_TUNE, m * 16, &buf));
+  // candidates: workgroup sizes per pass, then the step placement
+  std::vector<int> cand[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= d.dim) { cand[a].push_back(0); continue; }
+    const int tl = d.nl[a] / kE;
+    for (int t : {64, 128, 256})
+      if (t >= tl && t % tl == 0) cand[a].push_back(t);
+  }
+  gpe_options o;
+  set_default(&o);
+  o.precision = precision;
+  o.algorithm = GPE_ALG2;
+  o.k_init = 48;            // about 100 evaluations of each mode, no convergence test
+  o.k_sub = 48;
+  o.max_outer = 1;
+  o.tol = 0.0;
+  o.chunk = 32;
+  o.switch_window = 0;
+  double best = INFINITY;
+  TunedPlan bp{};
+  for (int t0 : cand[0])
+    for (int t1 : cand[1])
+      for (int t2 : cand[2])
+        for (int sa : {GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL}) {
+          o.threads[0] = t0; o.threads[1] = t1; o.threads[2] = t2;
+          o.step_at = sa;
+          double us = INFINITY;
+          for (int rep = 0; rep < 2; ++rep) {
+            CHK(begin_call(c));
+            CHK(upload(c, buf, h.data(), m * 16, 0));
+            CHK(end_call(c));
+            gpe_result r;
+            void* phis[1] = {buf};
+            CHK(solve_impl(c, 1, prob, &o, phis, &r));
+            if (r.nfe > 0) us = std::min(us, 1e3 * r.time_ms / r.nfe);
+          }
+          if (us < best) {
+            best = us;
+            bp.threads[0] = t0; bp.threads[1] = t1; bp.threads[2] = t2;
+            bp.step_at = sa;
+          }
+        }
+  bp.dim = prob->dim;
+  bp.bc = prob->bc;
+  bp.prec = precision;
+  for (int a = 0; a < 3; ++a) bp.n[a] = a < prob->dim ? prob->n[a] : 0;
+  bool replaced = false;
+  for (TunedPlan& t : c->plans)
+    if (find_plan(c, *prob, precision) == &t) { t = bp; replaced = true; }
+  if (!replaced) c->plans.push_back(bp);
+  if (threads_out)
+    for (int a = 0; a < 3; ++a) threads_out[a] = bp.threads[a];
+  if (step_at_out) *step_at_out = bp.step_at;
+  if (us_per_eval_out) *us_per_eval_out = best;
+  return GPE_OK;
 }
 
 int gpe_prolong(gpe_ctx* c, const gpe_problem* coarse, const gpe_problem* fine, const void* phi_c, void* phi_f) {

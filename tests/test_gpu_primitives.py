@@ -236,3 +236,14 @@ def test_apply_h_sine_eigenfunction(dev):
     out, _ = dev.apply_h(p, torch.from_numpy(f).cuda())
     lam = 0.5 * ((np.pi * l / 4.0) ** 2 + (np.pi * m / 4.0) ** 2)
     assert float(np.max(np.abs(out.cpu().numpy() - lam * f))) < 1e-12 * lam
+
+
+def test_apply_h_rotating_3d_eigenfunction(dev):
+    # the 3D rotation pin of the oracle on the GPU: eigenvalue 2 - Omega + gz/2
+    gz, om = 2.0, 0.4
+    p = W.Problem(dim=3, n=(64, 64, 64), lo=(-10.0,) * 3, hi=(10.0,) * 3, omega=om, gamma=(1.0, 1.0, gz))
+    x, y, z = disc.grid_coords(p)
+    f = (x + 1j * y) * np.exp(-(x * x + y * y) / 2) * np.exp(-gz * z * z / 2)
+    out, _ = dev.apply_h(p, torch.from_numpy(np.ascontiguousarray(f)).cuda())
+    lam = 2.0 - om + 0.5 * gz
+    assert float(np.max(np.abs(out.cpu().numpy() - lam * f))) < 1e-10

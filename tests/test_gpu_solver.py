@@ -345,3 +345,38 @@ def test_mixed_alg1_switches_to_fp64(dev):
     _, r0 = _gpu_solve(dev, p, phi0 + 0j, algorithm="alg1", tol=1e-10, precision="mixed",
                        switch_window=0, max_iter=3000)
     assert r0["status"] == 1 and r0["switch_iter"] == 0
+
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rotating_3d_small(dev, prec):
+    # 3D rotating Fourier problem (rotation about z), Algorithm 2 vs the oracle
+    p = W.Problem(dim=3, n=(32, 32, 32), lo=(-7.0,) * 3, hi=(7.0,) * 3, beta=300.0, omega=0.5,
+                  gamma=(1.0, 1.0, 1.5))
+    phi0 = W.rotating_initial(p, 0.5, 9) * np.exp(-0.75 * disc.grid_coords(p)[2] ** 2)
+    up = UnifiedProblem(p)
+    ref = regularized_newton(up, up.to_x(phi0), Options(tol=1e-7, max_outer=3000))
+    assert ref.converged
+    phi, res = _gpu_solve(dev, p, phi0, tol=1e-7, precision=prec, max_outer=3000)
+    assert res["status"] == 0, res
+    # both stop at residual 1e-7: mu (first order in the state's error) agrees
+    # to about that, E (second order) much closer
+    _compare(p, phi, ref.x, 1e-7, 1e-8, 1e-5)
+
+
+def test_autotune_plan(dev):
+    # the tuned plan is a valid configuration, and a later solve with open
+    # launch options uses it: bitwise the same as the plan given explicitly
+    # (a grid no other test uses, since the plan stays in the context)
+    p = W.Problem(dim=2, n=(128, 64), lo=(-10.0, -8.0), hi=(10.0, 8.0), beta=400.0, omega=0.3)
+    plan = dev.autotune(p, "mixed")
+    assert plan["us_per_eval"] > 0.0 and plan["step_at"] in (0, 1)
+    for a, n in enumerate(p.n):
+        t = plan["threads"][a]
+        assert t in (64, 128, 256) and t % (n // 8) == 0, plan
+    phi0 = W.rotating_initial(p, 0.3, 12)
+    phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed")
+    phi_b, rb = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed", threads=plan["threads"][:2] + [0],
+                           step_at=plan["step_at"])
+    assert ra["status"] == 0 and ra["nfe"] == rb["nfe"]
+    assert np.array_equal(phi_a, phi_b)

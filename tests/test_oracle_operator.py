@@ -48,6 +48,22 @@ def test_landau_levels_fix_rotation_sign(omega):
         assert np.max(np.abs(disc.h_lin(p, f) - lam * f)) < 1e-11
 
 
+@pytest.mark.parametrize("omega", [0.4, -0.7])
+def test_rotation_in_3d(omega):
+    # 3D: the rotation acts in the x-y plane only.  With V = (x^2 + y^2 +
+    # gz^2 z^2)/2, (x + iy) e^{-(x^2+y^2)/2} h_k(z) has eigenvalue
+    # 2 - Omega + (k + 1/2) gz for the trap levels h_0 = e^{-gz z^2/2},
+    # h_1 = z e^{-gz z^2/2}
+    gz = 2.0
+    p = W.Problem(dim=3, n=(64, 64, 64), lo=(-10.0,) * 3, hi=(10.0,) * 3, omega=omega,
+                  gamma=(1.0, 1.0, gz))
+    x, y, z = disc.grid_coords(p)
+    e = (x + 1j * y) * np.exp(-(x * x + y * y) / 2) * np.exp(-gz * z * z / 2)
+    for k, f in ((0, e), (1, z * e)):
+        lam = 2.0 - omega + (k + 0.5) * gz
+        assert np.max(np.abs(disc.h_lin(p, f) - lam * f)) < 1e-10
+
+
 def test_fourier_plane_waves_and_nyquist():
     # sin(2 pi k (x-a)/L) has -1/2 d_xx eigenvalue (2 pi k / L)^2 / 2 for
     # |k| < N/2; the Nyquist grid function (-1)^j gets (pi N / L)^2 / 2.
