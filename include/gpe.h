@@ -109,8 +109,8 @@ typedef struct gpe_options {
     double delta0, delta_min, delta_max;          /* regularisation delta */
     int32_t chunk;        /* evaluations per host check of the done flags (graph size) */
     int32_t use_graph;    /* 1: replay chunks as a captured hipGraph; 0: plain launches */
-    int32_t profile;      /* k > 0: time every k-th launch of the last-axis pass with HIP events
-                             (plain launches instead of a graph); 0: off */
+    int32_t profile;      /* k > 0: time the last-axis pass of every k-th evaluation with a pair of
+                             HIP events recorded around it (event nodes inside the graph); 0: off */
     int32_t real_field;   /* -1 (default): real arithmetic when Omega = 0 for every problem and
                              every phi0 has a zero imaginary part; 1: real arithmetic (Omega must
                              be 0); 0: complex.  In real arithmetic the imaginary parts are

@@ -535,7 +535,8 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd[i].m, phis[i], prec64);
   HIPCHK(hipGetLastError());
 
-  // profile: an event pair around the last-axis pass of every evaluation
+  // profile: an event pair around the last-axis pass of every k-th
+  // evaluation, recorded as external event nodes (also inside a graph)
   std::vector<hipEvent_t> pev;
   if (o.profile) {
     pev.resize(2 * (size_t)chunk, nullptr);
@@ -545,20 +546,28 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   auto sampled = [&](int64_t e) { return o.profile > 0 && e % o.profile == 0; };
   // block maps are only needed for batches (workgroup b is tile b of a single problem)
   auto bmap = [&](int ax) { return count == 1 ? nullptr : (const int2*)dbm[ax]; };
+  hipError_t enq_err = hipSuccess;
+  auto record = [&](hipEvent_t e) {
+    const hipError_t r = hipEventRecordWithFlags(e, c->s, hipEventRecordExternal);
+    if (r != hipSuccess && enq_err == hipSuccess) enq_err = r;
+  };
   auto enqueue_eval = [&](int k) {
     const bool prof = sampled(eval_index++);
-    hipEvent_t e0 = prof ? pev[2 * k] : nullptr, e1 = prof ? pev[2 * k + 1] : nullptr;
     if (dim == 1) {
+      if (prof) record(pev[2 * k]);
       launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
-                         c->twf, e0, e1);
+                         c->twf);
+      if (prof) record(pev[2 * k + 1]);
     } else {
       launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
                          c->twf);
       if (dim == 3)
         launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, S, bmap(1), c->twd,
                            c->twf);
+      if (prof) record(pev[2 * k]);
       launch_solver_pass(c->s, R_FINAL, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
-                         bmap(dim - 1), c->twd, c->twf, e0, e1);
+                         bmap(dim - 1), c->twd, c->twf);
+      if (prof) record(pev[2 * k + 1]);
     }
     if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S, prec64);
   };
@@ -568,11 +577,16 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  // (event records are not captured into graphs: profiling uses plain launches)
-  if (o.use_graph && !o.profile) {
+  if (o.use_graph) {
     HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < chunk; ++k) enqueue_eval(k);
     HIPCHK(hipStreamEndCapture(c->s, &graph));
+    if (enq_err != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      free_events();
+      g_last_error = std::string("graph capture: ") + hipGetErrorString(enq_err);
+      return GPE_EDEVICE;
+    }
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
   double pass_ms = 0.0;
@@ -588,6 +602,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       if (hipGraphLaunch(exec, c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
     } else {
       for (int k = 0; k < chunk; ++k) enqueue_eval(k);
+      if (enq_err != hipSuccess) { rc = GPE_EDEVICE; break; }
     }
     evals += chunk;
     if (hipMemcpyAsync(pin, dstate, sizeof(SolverState) * count, hipMemcpyDeviceToHost, c->s) != hipSuccess ||

@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ 
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[SA_COUNT * 16];
   const ProbDev P = probs[0];     // local copy: one batch of loads
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   switch (n) {

@@ -26,6 +26,10 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments arrive in scalar registers at dispatch (no load round
+    # trip before the first descriptor read); older firmware runs the
+    # compiler's fallback prologue instead
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-I", os.path.join(ROOT, "include"), "-I", HERE,
     "-Wno-unused-result",
 ]

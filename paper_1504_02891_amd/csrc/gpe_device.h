@@ -69,6 +69,19 @@ template <typename T> __device__ __forceinline__ void touch_lines(const T* p) {
   for (int i = 0; i < L; ++i) asm volatile("" ::"v"(w[i]));
 }
 
+// Workgroups go to the chip's 8 XCDs round robin (workgroup b to XCD b % 8),
+// each XCD with its own L2.  Renumbered by this bijection of [0, g), XCD x
+// works on one contiguous range of tiles: neighbouring tiles of a strided
+// pass read the same cache lines (a tile covers only part of a 128-byte
+// row), which are then fetched once into that XCD's L2 instead of once into
+// every XCD's.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_tile(int b, int g) {
+  const int x = b % kXcd, i = b / kXcd;
+  const int q = g / kXcd, r = g % kXcd;
+  return x * q + min(x, r) + i;
+}
+
 // Element i of a 2- or 3-array with i known only at run time, by selects, so
 // that a local copy of a descriptor is never indexed dynamically (which would
 // place it in scratch memory).

@@ -6,11 +6,9 @@
 #include "gpe_state.h"
 
 namespace gpe {
-// bmap: null for a single problem; ev0/ev1 (optional): events stamped at the
-// start and end of the dispatch
+// bmap: null for a single problem
 void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int threads, size_t smem,
-                        const ProbDev* probs, SolverState* st, const int2* bmap, const void* twd, const void* twf,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        const ProbDev* probs, SolverState* st, const int2* bmap, const void* twd, const void* twf);
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
 void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64);

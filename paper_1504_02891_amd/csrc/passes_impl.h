@@ -514,7 +514,8 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
                                                      const cx<float>* __restrict__ twf) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[SF_COUNT * 16];
-  const int2 bm = bmap ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+  const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int2 bm = bmap ? bmap[b] : make_int2(0, b);
   // local copies, read in one batch: the fields the pass needs pinned in
   // scalar registers
   ProbDev P = probs[bm.x];

@@ -35,18 +35,26 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_the_header(tmp_path):
+    # every field of the ctypes mirrors sits at the header's offset (a
+    # misplaced field would silently set a different C option)
     nat = _lib()
+    structs = (("gpe_problem", nat.Problem), ("gpe_options", nat.Options), ("gpe_result", nat.Result))
+    lines = []
+    for cname, py in structs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gpe.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gpe_problem),'
-                   ' sizeof(gpe_options), sizeof(gpe_result), offsetof(gpe_options, tau0),'
-                   ' offsetof(gpe_result, energy));return 0;}\n')
+                   'int main(void){' + "".join(lines) + 'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    C = ctypes
-    assert got == [C.sizeof(nat.Problem), C.sizeof(nat.Options), C.sizeof(nat.Result),
-                   nat.Options.tau0.offset, nat.Result.energy.offset]
+    want = []
+    for cname, py in structs:
+        want.append(ctypes.sizeof(py))
+        want.extend(getattr(py, fname).offset for fname, _ in py._fields_)
+    assert got == want
 
 
 def test_host_only_entry_points():
