@@ -262,8 +262,10 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
   const size_t elem = fp64 ? 16 : 8;
   Geom g[3];
   int maxt = 1;
+  // wider strided tiles (more columns per row segment) once the grid is large
+  const int th = d.m >= ((int64_t)1 << 20) ? 256 : kApplyThreads;
   for (int ax = 0; ax < d.dim; ++ax) {
-    g[ax] = pass_geom(d, ax, ax > 0, kApplyThreads, elem);
+    g[ax] = pass_geom(d, ax, ax > 0, th, elem);
     if (d.dim == 1) g[ax] = pass_geom(d, 0, false, 64, elem);
     d.tiles[ax] = g[ax].tiles;
     d.lanes[ax] = g[ax].lanes;
