@@ -8,8 +8,10 @@ HBM.  Default workload: the 2D rotating condensate (256x256 Fourier grid on
 [-12,12]^2, beta = 1000, Omega = 0.9), mixed precision, residual 1e-6.
 
 Prints one JSON line.  Extra fields: the roofline of the dominant kernel
-(the last-axis pass, timed with HIP events on the library's stream over the
-timed steps) and the float64 CPU oracle timed on a bounded sample.
+(the last-axis pass, timed with HIP events stamped by the dispatch of every
+k-th launch during the timed steps), the same solve on the plain
+float64 path, the H(phi)phi bandwidth of gpe_apply_h on a 256^3 grid, and
+the float64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -103,6 +105,34 @@ def recorded_traffic(workload_name, precision):
     return round(rec["traffic_bytes_per_launch"])
 
 
+def hphi_bandwidth(n=256, reps=10):
+    """H(phi)phi throughput through gpe_apply_h on an n^3 grid (the 3D lattice
+    problem's potential and beta), float32 and float64.  Bytes per
+    application: the canonical fused pass set (x pass: read phi, write t;
+    y pass: read phi and t, write t; z pass: read phi and t, write H phi) plus
+    the residual pass (read phi and H phi): 10 b M for element size b."""
+    import torch
+    import workloads as W
+    from paper_1504_02891_amd import api
+    p = W.Problem(dim=3, n=(n, n, n), lo=(-16.0,) * 3, hi=(16.0,) * 3, beta=1600.0, lattice_amp=100.0)
+    m = n ** 3
+    out = {"grid": f"{n}^3", "bytes_per_point": "10 b (b = 8 complex64, 16 complex128)"}
+    for prec, dt, b in (("mixed", torch.complex64, 8), ("fp64", torch.complex128, 16)):
+        x = (torch.randn(n, n, n, dtype=torch.float64, device="cuda") + 0j).to(dt)
+        api.apply_h(p, x, precision=prec)                  # warm-up (workspace, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.apply_h(p, x, precision=prec)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / reps
+        gbs = 10 * b * m / dt_s / 1e9
+        out[prec] = {"us_per_apply": round(1e6 * dt_s, 1), "gbs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "working_set_mb": round(3 * b * m / 2 ** 20)}
+        del x
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,9 +144,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="Newton-step cap per solve (lower it only for short profiler runs)")
-    ap.add_argument("--profile-every", type=int, default=8,
-                    help="time every k-th launch of the final pass with HIP events")
+    ap.add_argument("--profile-every", type=int, default=61,
+                    help="time every k-th launch of the final pass with HIP events (coprime with the "
+                         "64-evaluation chunk, so the samples cover every position in a chunk: the first "
+                         "evaluations after a host check run slower)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=1,
+                    help="timed solves of the same workload on the plain float64 path (0: skip)")
+    ap.add_argument("--no-hphi", action="store_true", help="skip the 256^3 H(phi)phi bandwidth measurement")
+    ap.add_argument("--only-hphi", action="store_true", help="only the 256^3 H(phi)phi bandwidth measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 10 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -129,6 +165,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 10}))
+        return
+    if a.only_hphi:
+        print(json.dumps({"hphi": hphi_bandwidth()}), flush=True)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -144,15 +183,19 @@ def main():
     phis = [torch.from_numpy(np.asarray(f, dtype=np.complex128)).to(dev) for f in phi0s]
     opts = dict(tol=a.tol, precision=a.precision, max_outer=a.max_outer)
 
-    def step(profile=0):
+    # timed steps: plain launches with every k-th last-axis pass timed by
+    # events stamped by its own dispatch (graph replay would need event
+    # nodes, which add their packets' time to the interval)
+    def step(profile):
+        kw = dict(opts, profile=profile, use_graph=0 if profile else 1)
         if len(probs) == 1:
-            out, r = api.solve(probs[0], phis[0], profile=profile, **opts)
+            out, r = api.solve(probs[0], phis[0], **kw)
             return [r]
-        outs, rs = api.solve_batched(probs, phis, profile=profile, **opts)
+        outs, rs = api.solve_batched(probs, phis, **kw)
         return rs
 
     for _ in range(a.warmup):
-        step()
+        step(a.profile_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
@@ -184,6 +227,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(a.workload, a.precision),
             "kernel": "k_solver_pass<R_FINAL>", "avg_launch_us": round(avg_ms * 1e3, 3),
+            "timing": f"dispatch-stamped HIP events on every {a.profile_every}th launch of the timed steps",
             "timed_launches": launches, "launches": nlaunch, "bytes_per_launch": round(bpl)}
 
     out = {
@@ -201,6 +245,26 @@ def main():
         "resid": [r["resid"] for r in last][:4],
         "roofline": roof,
     }
+    if a.fp64_steps > 0 and a.precision == "mixed":
+        o64 = dict(opts, precision="fp64")
+        if len(probs) == 1:
+            api.solve(probs[0], phis[0], **o64)            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r64 = []
+        for _ in range(a.fp64_steps):
+            if len(probs) == 1:
+                r64.append([api.solve(probs[0], phis[0], **o64)[1]])
+            else:
+                r64.append(api.solve_batched(probs, phis, **o64)[1])
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t0
+        out["fp64"] = {"value": round(a.fp64_steps * len(probs) / d64, 4), "unit": "solves/s",
+                       "converged": all(r["status"] == 0 for rs in r64 for r in rs),
+                       "nfe_per_solve": [r["nfe"] for r in r64[-1]],
+                       "energy": [r["energy"] for r in r64[-1]][:4], "resid": [r["resid"] for r in r64[-1]][:4]}
+    if not a.no_hphi:
+        out["hphi"] = hphi_bandwidth()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, phi0s, last[0]["nfe"], a.cpu_budget, opts)
     print(json.dumps(out), flush=True)

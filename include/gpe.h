@@ -110,7 +110,9 @@ typedef struct gpe_options {
     int32_t chunk;        /* evaluations per host check of the done flags (graph size) */
     int32_t use_graph;    /* 1: replay chunks as a captured hipGraph; 0: plain launches */
     int32_t profile;      /* k > 0: time the last-axis pass of every k-th evaluation with a pair of
-                             HIP events recorded around it (event nodes inside the graph); 0: off */
+                             HIP events: stamped by the kernel's own dispatch with plain launches
+                             (use_graph 0), event record nodes around it inside a graph (these
+                             add the event packets' time, a few microseconds); 0: off */
     int32_t real_field;   /* -1 (default): real arithmetic when Omega = 0 for every problem and
                              every phi0 has a zero imaginary part; 1: real arithmetic (Omega must
                              be 0); 0: complex.  In real arithmetic the imaginary parts are

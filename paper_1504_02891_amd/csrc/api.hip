@@ -296,8 +296,8 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
   }
   HIPCHK(hipGetLastError());
   if (a.kind == 0) {
-    launch_apply_resid(c->s, nr, P, a.in, a.out, (double*)rpart, fp64);
-    launch_apply_finalize(c->s, P, (const double*)rpart, nr, (double*)out);
+    launch_apply_resid(c->s, nr, P, a.in, a.out, (double*)rpart, (double*)out, fp64);
+    launch_apply_finalize(c->s, (const double*)rpart, nr, (double*)out);
     HIPCHK(hipGetLastError());
     if (scalars) {
       void* pin;
@@ -538,7 +538,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   HIPCHK(hipGetLastError());
 
   // profile: an event pair around the last-axis pass of every k-th
-  // evaluation, recorded as external event nodes (also inside a graph)
+  // evaluation: stamped by the dispatch itself with plain launches, event
+  // record nodes inside a graph (these also count the event packets' own
+  // time, a few microseconds)
   std::vector<hipEvent_t> pev;
   if (o.profile) {
     pev.resize(2 * (size_t)chunk, nullptr);
@@ -549,28 +551,40 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   // block maps are only needed for batches (workgroup b is tile b of a single problem)
   auto bmap = [&](int ax) { return count == 1 ? nullptr : (const int2*)dbm[ax]; };
   hipError_t enq_err = hipSuccess;
+  // an event record on the stream, or, while capturing, an event-record node
+  // appended to the captured graph after the stream's current frontier
   auto record = [&](hipEvent_t e) {
-    const hipError_t r = hipEventRecordWithFlags(e, c->s, hipEventRecordExternal);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipGraph_t cg = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t ndeps = 0;
+    hipError_t r = hipStreamGetCaptureInfo_v2(c->s, &cs, nullptr, &cg, &deps, &ndeps);
+    if (r == hipSuccess && cs == hipStreamCaptureStatusActive) {
+      hipGraphNode_t node;
+      r = hipGraphAddEventRecordNode(&node, cg, deps, ndeps, e);
+      if (r == hipSuccess) r = hipStreamUpdateCaptureDependencies(c->s, &node, 1, hipStreamSetCaptureDependencies);
+    } else if (r == hipSuccess) {
+      r = hipEventRecord(e, c->s);
+    }
     if (r != hipSuccess && enq_err == hipSuccess) enq_err = r;
   };
+  bool capturing = false;
   auto enqueue_eval = [&](int k) {
     const bool prof = sampled(eval_index++);
-    if (dim == 1) {
-      if (prof) record(pev[2 * k]);
-      launch_solver_pass(c->s, R_SOLO, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
-                         c->twf);
-      if (prof) record(pev[2 * k + 1]);
-    } else {
+    const bool nodes = prof && capturing;                    // event record nodes around the pass
+    hipEvent_t e0 = prof && !capturing ? pev[2 * k] : nullptr, e1 = prof && !capturing ? pev[2 * k + 1] : nullptr;
+    const int last = dim == 1 ? R_SOLO : R_FINAL;
+    if (dim > 1) {
       launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
                          c->twf);
       if (dim == 3)
         launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, S, bmap(1), c->twd,
                            c->twf);
-      if (prof) record(pev[2 * k]);
-      launch_solver_pass(c->s, R_FINAL, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
-                         bmap(dim - 1), c->twd, c->twf);
-      if (prof) record(pev[2 * k + 1]);
     }
+    if (nodes) record(pev[2 * k]);
+    launch_solver_pass(c->s, last, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
+                       bmap(dim - 1), c->twd, c->twf, e0, e1);
+    if (nodes) record(pev[2 * k + 1]);
     if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S, prec64);
   };
   auto free_events = [&]() {
@@ -581,7 +595,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   hipGraphExec_t exec = nullptr;
   if (o.use_graph) {
     HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+    capturing = true;
     for (int k = 0; k < chunk; ++k) enqueue_eval(k);
+    capturing = false;
     HIPCHK(hipStreamEndCapture(c->s, &graph));
     if (enq_err != hipSuccess) {
       (void)hipGraphDestroy(graph);

@@ -74,9 +74,9 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
       }
     block_reduce<SA_COUNT_SUM, 1>(acc, red);
     if (threadIdx.x == 0) {
-      const int64_t o = (int64_t)tile * SA_COUNT;
+      const int64_t nt = pick3(P.tiles, P.dim - 1);
 #pragma unroll
-      for (int i = 0; i < SA_COUNT; ++i) gst<double>(P.partF, o + i, acc[i]);
+      for (int i = 0; i < SA_COUNT; ++i) gst<double>(P.partF, i * nt + tile, acc[i]);
     }
   }
 }

@@ -374,7 +374,11 @@ __device__ __forceinline__ void wave_reduce_k(double* acc, unsigned maxmask) {
   for (int i = 0; i < K; ++i) acc[i] = lane63(acc[i]);
 }
 
-// Fixed-order reduction of part[i*stride + s] over i < count, for slots
+// Partial sums are stored slot-major, part[s * count + i] for slot s of
+// workgroup (tile) i, so that reading one slot of consecutive tiles is
+// coalesced.
+//
+// Fixed-order reduction of part[s * count + i] over i < count, for slots
 // s < NSLOT (a max where bit s of `maxmask` is set, else a sum), by one
 // wavefront: lane l accumulates i = l, l+64, l+128, ... in turn, then the
 // lanes are combined by wave_reduce_k.  Loads go out in batches of B per
@@ -382,7 +386,7 @@ __device__ __forceinline__ void wave_reduce_k(double* acc, unsigned maxmask) {
 // calling wavefront gets the result; every caller reducing the same
 // partials gets the same bits.
 template <int NSLOT>
-__device__ __forceinline__ void wave_reduce_partials(const double* part, int count, int stride, unsigned maxmask,
+__device__ __forceinline__ void wave_reduce_partials(const double* part, int count, unsigned maxmask,
                                                      double* acc) {
   constexpr int B = NSLOT <= 4 ? 8 : 4;
   const int l = threadIdx.x & 63;
@@ -394,7 +398,7 @@ __device__ __forceinline__ void wave_reduce_partials(const double* part, int cou
     for (int j = 0; j < B; ++j) {
       const int64_t i = min(b0 + l + 64 * j, count - 1);
 #pragma unroll
-      for (int s = 0; s < NSLOT; ++s) v[j][s] = gld<double>(part, i * stride + s);
+      for (int s = 0; s < NSLOT; ++s) v[j][s] = gld<double>(part, (int64_t)s * count + i);
     }
 #pragma unroll
     for (int j = 0; j < B; ++j)

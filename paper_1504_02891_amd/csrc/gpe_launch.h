@@ -6,18 +6,22 @@
 #include "gpe_state.h"
 
 namespace gpe {
-// bmap: null for a single problem
+// bmap: null for a single problem; ev0/ev1 (optional, plain launches only):
+// events stamped by the dispatch itself at the kernel's start and end
 void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int threads, size_t smem,
-                        const ProbDev* probs, SolverState* st, const int2* bmap, const void* twd, const void* twf);
+                        const ProbDev* probs, SolverState* st, const int2* bmap, const void* twd, const void* twf,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
 void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64);
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64);
 void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
                       int prec64);
+// the energy sums into out[0, 1, 3..9], then per-block residual maxima (rpart)
 void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const void* phi, const void* hphi,
-                        double* rpart, int fp64);
-void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* rpart, int nr, double* out);
+                        double* rpart, double* out, int fp64);
+// out[2] = sqrt of the largest rpart entry
+void launch_apply_finalize(hipStream_t s, const double* rpart, int nr, double* out);
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
                     double* part, double* coeffs);
 // per-block max |Im x_i| of a complex128 array (part[nblk])

@@ -89,8 +89,8 @@ struct ProbDev {
   void* xk;              // outer iterate X_k (complex double)
   void* gk;              // G_k = grad F(X_k) (complex double)
   void* t;               // accumulator of the directional passes (complex double sized)
-  double* part1;         // [tiles[0]][S1_COUNT]
-  double* partF;         // [tiles[dim-1]][SF_COUNT]
+  double* part1;         // [S1_COUNT][tiles[0]] (slot-major)
+  double* partF;         // [SF_COUNT][tiles[dim-1]] (slot-major)
   int32_t* ticket;       // workgroups of the final pass done (reset by the last one)
   const void* user_in;   // apply / init input
   void* user_out;        // apply output

@@ -1,5 +1,6 @@
 // One solver pass (role GPE_ROLE, precision GPE_PREC64) per object file, so
 // the build compiles the pass variants in parallel.
+#include <hip/hip_ext.h>
 #include "gpe_launch.h"
 #include "passes_impl.h"
 
@@ -15,8 +16,15 @@
 namespace gpe {
 void GPE_CAT(launch_solver_pass_r, GPE_ROLE, GPE_PREC64)(hipStream_t s, int nblocks, int threads, size_t smem,
                                                          const ProbDev* probs, SolverState* st,
-                                                         const int2* bmap, const void* twd, const void* twf) {
-  hipLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0)>), dim3(nblocks), dim3(threads), smem, s, probs, st,
-                     bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+                                                         const int2* bmap, const void* twd, const void* twf,
+                                                         hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0) {
+    // events stamped by the dispatch itself (start and end of this kernel)
+    hipExtLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0)>), dim3(nblocks), dim3(threads), smem, s, ev0,
+                          ev1, 0, probs, st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+  } else {
+    hipLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0)>), dim3(nblocks), dim3(threads), smem, s, probs,
+                       st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+  }
 }
 }  // namespace gpe

@@ -17,8 +17,8 @@ __global__ void __launch_bounds__(64) k_step(const ProbDev* __restrict__ probs, 
   touch_lines(states + blockIdx.x);
   if (L.mode == M_IDLE) return;
   double r1[S1_COUNT], rf[SF_COUNT];
-  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1);
-  wave_reduce_partials<SF_COUNT>(P.partF, pick3(P.tiles, P.dim - 1), SF_COUNT, 1u << SF_SMAX, rf);
+  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], 1u << S1_RMAX, r1);
+  wave_reduce_partials<SF_COUNT>(P.partF, pick3(P.tiles, P.dim - 1), 1u << SF_SMAX, rf);
   if (threadIdx.x == 0) {
     step_logic(P, L, r1, rf, prec64);
     states[blockIdx.x] = L;
@@ -50,22 +50,62 @@ __global__ void k_write_phi(const ProbDev* probs, const SolverState* states, int
 }
 
 // ---- apply_h outputs: residual max |H phi - mu phi| and the scalar summary ----
-__device__ static void apply_energy(const ProbDev& P, double* red, double* kin, double* pot, double* quart) {
-  const int tf = P.tiles[P.dim - 1];
-  *kin = fixed_reduce(P.partF, tf, SA_COUNT, SA_KIN, false, red);
-  *pot = fixed_reduce(P.partF, tf, SA_COUNT, SA_POT, false, red);
-  *quart = fixed_reduce(P.partF, tf, SA_COUNT, SA_QUART, false, red);
+// Fixed-order reduction of slot-major partials part[s * count + i], i < count,
+// s < NSLOT (the last NM slots maxima) by one workgroup of kSumThreads
+// threads: thread j takes i = j, j + kSumThreads, ... in turn (loads in
+// batches), then the block reduction.  Thread 0 gets the result.
+constexpr int kSumThreads = 1024;
+template <int NS, int NM>
+__device__ __forceinline__ void block_sum_partials(const double* part, int count, double* acc, double* red) {
+  constexpr int NSLOT = NS + NM;
+  constexpr int B = NSLOT >= 4 ? 4 : 8;     // loads in flight per slot (128 registers at 1024 threads)
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;
+  for (int b0 = 0; b0 < count; b0 += B * kSumThreads) {
+    double v[B][NSLOT];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int64_t i = min(b0 + (int)threadIdx.x + j * kSumThreads, count - 1);
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) v[j][s] = gld<double>(part, (int64_t)s * count + i);
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (b0 + (int)threadIdx.x + j * kSumThreads < count)
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) acc[s] = s < NS ? acc[s] + v[j][s] : fmax(acc[s], v[j][s]);
+  }
+  block_reduce<NS, NM>(acc, red);
+}
+
+// The energy sums of the last pass: out[0] = E, out[1] = mu, out[3..9] as
+// documented for gpe_apply_h (out[2], the residual, comes from the last kernel)
+__global__ void __launch_bounds__(kSumThreads) k_apply_sums(const ProbDev* probs, double* __restrict__ out) {
+  __shared__ double red[SA_COUNT * 16];
+  const ProbDev& P = probs[0];
+  double acc[SA_COUNT];
+  block_sum_partials<SA_COUNT_SUM, 1>(P.partF, pick3(P.tiles, P.dim - 1), acc, red);
+  if (threadIdx.x == 0) {
+    const double e = P.hvol * (acc[SA_KIN] + acc[SA_POT] + 0.5 * P.beta * acc[SA_QUART]);
+    out[0] = e;
+    out[1] = e + 0.5 * P.beta * P.hvol * acc[SA_QUART];
+    out[3] = P.hvol * acc[SA_NORM];
+    out[4] = sqrt(P.hvol * acc[SA_X2]);
+    out[5] = sqrt(P.hvol * acc[SA_Y2]);
+    out[6] = sqrt(P.hvol * acc[SA_Z2]);
+    out[7] = acc[SA_MAXD];
+    out[8] = P.hvol * acc[SA_KIN];
+    out[9] = P.hvol * acc[SA_POT];
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply_resid(const ProbDev* probs, const cx<T>* __restrict__ phi,
-                                                     const cx<T>* __restrict__ hphi, double* __restrict__ rpart) {
+                                                     const cx<T>* __restrict__ hphi, const double* __restrict__ out,
+                                                     double* __restrict__ rpart) {
   __shared__ double red[16];
   const ProbDev& P = probs[0];
-  double kin, pot, quart;
-  apply_energy(P, red, &kin, &pot, &quart);
-  const double e = P.hvol * (kin + pot + 0.5 * P.beta * quart);
-  const double mu = e + 0.5 * P.beta * P.hvol * quart;
+  const double mu = out[1];
   double r = 0.0;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
     const cx<double> u = cvt<double>(phi[g]), h = cvt<double>(hphi[g]);
@@ -76,33 +116,12 @@ __global__ void __launch_bounds__(256) k_apply_resid(const ProbDev* probs, const
   if (threadIdx.x == 0) rpart[blockIdx.x] = acc[0];
 }
 
-__global__ void __launch_bounds__(64) k_apply_finalize(const ProbDev* probs, const double* __restrict__ rpart,
-                                                       int nr, double* __restrict__ out) {
-  __shared__ double red[4];
-  const ProbDev& P = probs[0];
-  double kin, pot, quart;
-  apply_energy(P, red, &kin, &pot, &quart);
-  const int tf = P.tiles[P.dim - 1];
-  double s[4];
-  s[0] = fixed_reduce(P.partF, tf, SA_COUNT, SA_NORM, false, red);
-  s[1] = fixed_reduce(P.partF, tf, SA_COUNT, SA_X2, false, red);
-  s[2] = fixed_reduce(P.partF, tf, SA_COUNT, SA_Y2, false, red);
-  s[3] = fixed_reduce(P.partF, tf, SA_COUNT, SA_Z2, false, red);
-  const double maxd = fixed_reduce(P.partF, tf, SA_COUNT, SA_MAXD, true, red);
-  const double rmax = fixed_reduce(rpart, nr, 1, 0, true, red);
-  if (threadIdx.x == 0) {
-    const double e = P.hvol * (kin + pot + 0.5 * P.beta * quart);
-    out[0] = e;
-    out[1] = e + 0.5 * P.beta * P.hvol * quart;
-    out[2] = sqrt(rmax);
-    out[3] = P.hvol * s[0];
-    out[4] = sqrt(P.hvol * s[1]);
-    out[5] = sqrt(P.hvol * s[2]);
-    out[6] = sqrt(P.hvol * s[3]);
-    out[7] = maxd;
-    out[8] = P.hvol * kin;
-    out[9] = P.hvol * pot;
-  }
+__global__ void __launch_bounds__(kSumThreads) k_apply_finalize(const double* __restrict__ rpart, int nr,
+                                                                double* __restrict__ out) {
+  __shared__ double red[16];
+  double acc[1];
+  block_sum_partials<0, 1>(rpart, nr, acc, red);
+  if (threadIdx.x == 0) out[2] = sqrt(acc[0]);
 }
 
 // ---- largest |Im| of the initial data (choice of real arithmetic) ----
@@ -129,9 +148,9 @@ __global__ void __launch_bounds__(256) k_retract_reduce(const cx<double>* __rest
   }
   block_reduce<3, 0>(acc, red);
   if (threadIdx.x == 0) {
-    part[blockIdx.x * 3 + 0] = acc[0];
-    part[blockIdx.x * 3 + 1] = acc[1];
-    part[blockIdx.x * 3 + 2] = acc[2];
+    part[0 * gridDim.x + blockIdx.x] = acc[0];
+    part[1 * gridDim.x + blockIdx.x] = acc[1];
+    part[2 * gridDim.x + blockIdx.x] = acc[2];
   }
 }
 
@@ -140,9 +159,9 @@ __global__ void __launch_bounds__(256) k_retract_apply(const cx<double>* __restr
                                                        const double* __restrict__ part, int np,
                                                        double* __restrict__ coeffs) {
   __shared__ double red[4];
-  const double a = fixed_reduce(part, np, 3, 0, false, red);
-  const double nx = fixed_reduce(part, np, 3, 1, false, red);
-  const double ng = fixed_reduce(part, np, 3, 2, false, red);
+  const double a = fixed_reduce(part, np, 0, false, red);
+  const double nx = fixed_reduce(part, np, 1, false, red);
+  const double ng = fixed_reduce(part, np, 2, false, red);
   const double den = 1.0 - tau * tau * a * a + tau * tau * nx * ng;
   const double p = ((1.0 + tau * a) * (1.0 + tau * a) - tau * tau * nx * ng) / den;
   const double q = -2.0 * tau * nx / den;
@@ -215,14 +234,15 @@ void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st
   else hipLaunchKernelGGL(k_write_phi<float>, dim3(blocks), dim3(256), 0, s, probs, st, pi, (cx<double>*)phi);
 }
 void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const void* phi, const void* hphi,
-                        double* rpart, int fp64) {
+                        double* rpart, double* out, int fp64) {
+  hipLaunchKernelGGL(k_apply_sums, dim3(1), dim3(kSumThreads), 0, s, probs, out);
   if (fp64) hipLaunchKernelGGL(k_apply_resid<double>, dim3(nblk), dim3(256), 0, s, probs,
-                               (const cx<double>*)phi, (const cx<double>*)hphi, rpart);
+                               (const cx<double>*)phi, (const cx<double>*)hphi, (const double*)out, rpart);
   else hipLaunchKernelGGL(k_apply_resid<float>, dim3(nblk), dim3(256), 0, s, probs,
-                          (const cx<float>*)phi, (const cx<float>*)hphi, rpart);
+                          (const cx<float>*)phi, (const cx<float>*)hphi, (const double*)out, rpart);
 }
-void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* rpart, int nr, double* out) {
-  hipLaunchKernelGGL(k_apply_finalize, dim3(1), dim3(64), 0, s, probs, rpart, nr, out);
+void launch_apply_finalize(hipStream_t s, const double* rpart, int nr, double* out) {
+  hipLaunchKernelGGL(k_apply_finalize, dim3(1), dim3(kSumThreads), 0, s, rpart, nr, out);
 }
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
                     double* part, double* coeffs) {

@@ -140,19 +140,18 @@ __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const T
 
 // One slot of the fixed-order reduction (the same bits as that slot of the
 // multi-slot call), computed by every wavefront of the caller on its own.
-__device__ __forceinline__ double wave_reduce_slot(const double* part, int count, int stride, int slot,
-                                                   bool is_max) {
+__device__ __forceinline__ double wave_reduce_slot(const double* part, int count, int slot, bool is_max) {
   double a[1];
-  wave_reduce_partials<1>(part + slot, count, stride, is_max ? 1u : 0u, a);
+  wave_reduce_partials<1>(part + (int64_t)slot * count, count, is_max ? 1u : 0u, a);
   return a[0];
 }
 // Fixed-order reduction for a whole workgroup: the first wavefront reduces,
 // every thread gets the result through `red`.
 template <int NSLOT>
-__device__ __forceinline__ void reduce_partials(const double* part, int count, int stride, unsigned maxmask,
-                                                double* out, double* red) {
+__device__ __forceinline__ void reduce_partials(const double* part, int count, unsigned maxmask, double* out,
+                                                double* red) {
   if (threadIdx.x < 64) {
-    wave_reduce_partials<NSLOT>(part, count, stride, maxmask, out);
+    wave_reduce_partials<NSLOT>(part, count, maxmask, out);
     if (threadIdx.x == 0)
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s) red[s] = out[s];
@@ -162,10 +161,9 @@ __device__ __forceinline__ void reduce_partials(const double* part, int count, i
   for (int s = 0; s < NSLOT; ++s) out[s] = red[s];
   __syncthreads();
 }
-__device__ __forceinline__ double fixed_reduce(const double* part, int count, int stride, int slot,
-                                               bool is_max, double* red) {
+__device__ __forceinline__ double fixed_reduce(const double* part, int count, int slot, bool is_max, double* red) {
   double r[1];
-  reduce_partials<1>(part + slot, count, stride, is_max ? 1u : 0u, r, red);
+  reduce_partials<1>(part + (int64_t)slot * count, count, is_max ? 1u : 0u, r, red);
   return r[0];
 }
 __device__ __forceinline__ double renorm_c(const SolverState& S, double ny) {
@@ -366,7 +364,7 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   double c = 1.0, n_hat = 1.0;
   if constexpr (ROLE == R_FINAL) {
     // every wavefront reduces the first pass's norm partials itself
-    const double ny = wave_reduce_slot(P.part1, P.tiles[0], S1_COUNT, S1_NY, false);
+    const double ny = wave_reduce_slot(P.part1, P.tiles[0], S1_NY, false);
     c = renorm_c(S, ny);
     n_hat = c * c * ny;
   }
@@ -402,10 +400,10 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
     block_reduce<2, 1>(acc, red);
     if (threadIdx.x == 0) {
-      const int64_t o = (int64_t)tile * S1_COUNT;
-      gst<double>(P.part1, o + S1_NY, acc[0]);
-      gst<double>(P.part1, o + S1_NP2, acc[1]);
-      gst<double>(P.part1, o + S1_RMAX, acc[2]);
+      const int64_t nt = P.tiles[0];
+      gst<double>(P.part1, S1_NY * nt + tile, acc[0]);
+      gst<double>(P.part1, S1_NP2 * nt + tile, acc[1]);
+      gst<double>(P.part1, S1_RMAX * nt + tile, acc[2]);
     }
   } else if constexpr (ROLE == R_MID) {
 #pragma unroll
@@ -426,9 +424,9 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
     acc[SF_SMAX] = af.smax;
     block_reduce<SF_COUNT_SUM, 1>(acc, red);
     if (threadIdx.x == 0) {
-      const int64_t o = (int64_t)tile * SF_COUNT;
+      const int64_t nt = pick3(P.tiles, P.dim - 1);
 #pragma unroll
-      for (int i = 0; i < SF_COUNT; ++i) gst<double>(P.partF, o + i, acc[i]);
+      for (int i = 0; i < SF_COUNT; ++i) gst<double>(P.partF, i * nt + tile, acc[i]);
     }
   }
 }
@@ -454,8 +452,8 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, 
   if (!is_last || threadIdx.x >= 64) return;
   touch_lines(Sg);
   double r1[S1_COUNT], rf[SF_COUNT];
-  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], S1_COUNT, 1u << S1_RMAX, r1);
-  wave_reduce_partials<SF_COUNT>(P.partF, ntiles, SF_COUNT, 1u << SF_SMAX, rf);
+  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], 1u << S1_RMAX, r1);
+  wave_reduce_partials<SF_COUNT>(P.partF, ntiles, 1u << SF_SMAX, rf);
   if (threadIdx.x == 0) {
     SolverState L = *Sg;
     step_logic(P, L, r1, rf, prec64);
