@@ -184,7 +184,10 @@ const char* gpe_last_error(void);
  *   scalars    HOST double[10] out or NULL: E_h(phi), mu = E + beta/2 int|phi|^4,
  *              ||H(phi)phi - mu phi||_inf, ||phi||_h^2, rms x, y, z, max|phi|^2,
  *              kinetic+rotation part of E, potential part of E.
- * Blocks until the scalars are on the host when scalars != NULL.
+ * Blocks until the scalars are on the host when scalars != NULL.  With
+ * scalars == NULL and the same problem as the context's previous apply call
+ * (nothing to upload) the call only enqueues work and returns at once; the
+ * scalars are still computed on the device.
  */
 int gpe_apply_h(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision,
                 const void* phi, void* h_phi, double* scalars);

@@ -120,17 +120,23 @@ SCALAR_NAMES = ("energy", "mu", "resid", "norm2", "rms_x", "rms_y", "rms_z", "ma
                 "e_kin", "e_pot")
 
 
-def apply_h(p, phi, precision="fp64", v=None):
-    """H(phi) phi on the problem's grid; returns (h_phi, scalars dict)."""
+def apply_h(p, phi, precision="fp64", v=None, scalars=True, out=None):
+    """H(phi) phi on the problem's grid; returns (h_phi, scalars dict), or
+    (h_phi, None) with ``scalars=False`` (no host wait: the call only
+    enqueues work on the current stream).  ``out``: optional preallocated
+    result tensor like ``phi``."""
     prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
     dt = torch.complex128 if prec == N.GPE_PREC_FP64 else torch.complex64
     _dev_tensor(phi, dt, "phi", p)
-    out = torch.empty_like(phi)
-    sc = (C.c_double * 10)()
+    if out is None:
+        out = torch.empty_like(phi)
+    else:
+        _dev_tensor(out, dt, "out", p)
+    sc = (C.c_double * 10)() if scalars else None
     ps = problem_struct(p, v)
     _check(N.lib().gpe_apply_h(context(phi.device.index), C.byref(ps), prec, C.c_void_p(phi.data_ptr()),
                                C.c_void_p(out.data_ptr()), sc), "gpe_apply_h")
-    return out, dict(zip(SCALAR_NAMES, list(sc)))
+    return out, (dict(zip(SCALAR_NAMES, list(sc))) if scalars else None)
 
 
 def hess_vec(p, x_k, s, delta, v=None):

@@ -61,6 +61,8 @@ struct gpe_ctx {
   size_t ws_size[WS_COUNT] = {};
   void* pinned = nullptr;       // host staging for uploads / small downloads
   size_t pinned_size = 0;
+  bool staged = false;          // an upload from the staging buffer may still be pending
+  std::vector<unsigned char> apply_key;   // descriptor + V tables last uploaded for apply calls
 };
 
 namespace {
@@ -74,6 +76,7 @@ int ws_get(gpe_ctx* c, int slot, size_t bytes, void** out) {
       c->ws[slot] = nullptr;
       c->ws_size[slot] = 0;
     }
+    c->apply_key.clear();
     size_t b = bytes + bytes / 8;
     if (hipMalloc(&c->ws[slot], b) != hipSuccess) {
       (void)hipGetLastError();
@@ -100,19 +103,29 @@ int pinned_get(gpe_ctx* c, size_t bytes, void** out) {
   return GPE_OK;
 }
 
-// Stream-ordered upload through the pinned staging buffer.  The caller has
-// synchronised the context stream, so the staging memory is free.
+// Stream-ordered upload through the pinned staging buffer.  begin_call has
+// waited for any upload of an earlier call, and uploads within one call use
+// disjoint staging offsets, so the staging memory is free.
 int upload(gpe_ctx* c, void* dst, const void* src, size_t bytes, size_t staging_off) {
   void* pin;
   CHK(pinned_get(c, staging_off + bytes, &pin));
   std::memcpy((char*)pin + staging_off, src, bytes);
   HIPCHK(hipMemcpyAsync(dst, (char*)pin + staging_off, bytes, hipMemcpyHostToDevice, c->s));
+  c->staged = true;
   return GPE_OK;
 }
 
+// Every entry point starts here: the context stream waits for the caller's
+// stream, and the host waits for the context stream only while an upload of
+// an earlier call may still read the staging buffer.  A call that uploads
+// nothing and reads nothing back (an apply with unchanged problem and no
+// scalars) is therefore fully asynchronous.
 int begin_call(gpe_ctx* c) {
   HIPCHK(hipSetDevice(c->device));
-  HIPCHK(hipStreamSynchronize(c->s));
+  if (c->staged) {
+    HIPCHK(hipStreamSynchronize(c->s));
+    c->staged = false;
+  }
   HIPCHK(hipEventRecord(c->ev_in, c->user));
   HIPCHK(hipStreamWaitEvent(c->s, c->ev_in, 0));
   return GPE_OK;
@@ -273,18 +286,31 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
   }
   void *t, *part, *vax, *pd, *rpart, *out;
   CHK(ws_get(c, WS_APPLY_T, (size_t)d.m * elem, &t));
-  CHK(ws_get(c, WS_APPLY_PART, (size_t)maxt * SA_COUNT * sizeof(double), &part));
+  // one partial per wavefront of the last pass
+  const Geom& gl = g[d.dim - 1];
+  const int nsum = gl.tiles * ((gl.threads + 63) / 64);
+  CHK(ws_get(c, WS_APPLY_PART, (size_t)nsum * SA_COUNT * sizeof(double), &part));
   CHK(ws_get(c, WS_APPLY_VAXIS, vaxis.size() * sizeof(double), &vax));
   CHK(ws_get(c, WS_APPLY_PROB, sizeof(ProbDev), &pd));
-  const int nr = (int)std::min<int64_t>((d.m + 255) / 256, 1024);
-  CHK(ws_get(c, WS_APPLY_RPART, nr * sizeof(double), &rpart));
-  CHK(ws_get(c, WS_APPLY_OUT, 16 * sizeof(double), &out));
+  const int nr = (int)std::min<int64_t>((d.m + 255) / 256, fp64 ? 1024 : 2048);   // residual blocks
+  CHK(ws_get(c, WS_APPLY_RPART, (size_t)nr * SR_COUNT * sizeof(double), &rpart));
+  CHK(ws_get(c, WS_APPLY_OUT, (16 + SA_COUNT) * sizeof(double), &out));   // scalars, then slot totals
   d.t = t;
   d.partF = (double*)part;
   d.part1 = (double*)part;
   d.v_axis = (const double*)vax;
-  CHK(upload(c, vax, vaxis.data(), vaxis.size() * sizeof(double), 0));
-  CHK(upload(c, pd, &d, sizeof(d), vaxis.size() * sizeof(double)));
+  // upload the descriptor and tables only when they differ from the last ones
+  // (both workspaces have fixed sizes, so their contents persist)
+  const size_t vb = vaxis.size() * sizeof(double);
+  std::vector<unsigned char> key(sizeof(d) + vb);
+  std::memcpy(key.data(), &d, sizeof(d));
+  std::memcpy(key.data() + sizeof(d), vaxis.data(), vb);
+  if (key != c->apply_key) {
+    c->apply_key.clear();
+    CHK(upload(c, vax, vaxis.data(), vb, 0));
+    CHK(upload(c, pd, &d, sizeof(d), vb));
+    c->apply_key.swap(key);
+  }
   const void* tw = fp64 ? c->twd : c->twf;
   const ProbDev* P = (const ProbDev*)pd;
   if (d.dim == 1) {
@@ -296,8 +322,9 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
   }
   HIPCHK(hipGetLastError());
   if (a.kind == 0) {
-    launch_apply_resid(c->s, nr, P, a.in, a.out, (double*)rpart, (double*)out, fp64);
-    launch_apply_finalize(c->s, (const double*)rpart, nr, (double*)out);
+    double* tot = (double*)out + 16;
+    launch_apply_resid(c->s, nr, P, nsum, a.in, a.out, (double*)rpart, tot, fp64);
+    launch_apply_finalize(c->s, P, tot, (const double*)rpart, nr, (double*)out);
     HIPCHK(hipGetLastError());
     if (scalars) {
       void* pin;

@@ -4,32 +4,53 @@
 #pragma once
 #include "passes_impl.h"
 
+
 namespace gpe {
 
-template <int N, int ROLE, typename T>
+// KIND 0: H(phi) phi with the energy sums; KIND 1: Hessian-vector product.
+// Only the epilogue roles (FINAL, SOLO) depend on KIND.
+template <int N, int ROLE, typename T, int KIND>
 __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A, int tile, cx<T>* lds,
                                            const cx<T>* tw1024, double* red) {
   constexpr int E = Tile<N>::E;
   constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   const int ax = role_axis(ROLE, P.dim);
   constexpr bool EPI = (ROLE == R_FINAL || ROLE == R_SOLO);
+  constexpr bool HESS = EPI && KIND == 1;
   const Tile<N> Tl(P, ax, HAS_T, tile);
   TwiddleFetch<N, T> twf;
   twf.fetch(tw1024);
-  // one batch of loads: input, accumulator, potential, X_k (Hessian-vector)
+  // loads: the input first; the accumulator, X_k (Hessian-vector) and the
+  // potential of the epilogue roles with it (float64: 0) or after the
+  // inverse transform (float32: 2).  Late loads keep the float32 final pass
+  // at three waves per SIMD (measured 128 vs 164 us at 256^3); the float64
+  // pass is slightly faster with every load issued up front.
+  constexpr int LOADS_AT = EPI && sizeof(T) == 4 ? 2 : 0;
   cx<T> u[E], tv[E], v[E];
-  cx<double> xk[E];
+  cx<double> xk[HESS ? E : 1];
   double vp[E];
+  auto late_loads = [&]() {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    u[e] = ld<T>(A.in, Tl.g(e));
-    if constexpr (HAS_T) tv[e] = ld<T>(P.t, Tl.g(e));
-    if constexpr (EPI) xk[e] = A.kind == 1 ? ld<double>(A.xk, Tl.g(e)) : cx<double>{0.0, 0.0};
-    v[e] = cvt<T>(Tl.sgn(e) * cvt<double>(u[e]));
+    for (int e = 0; e < E; ++e) {
+      if constexpr (HAS_T) tv[e] = ld<T>(P.t, Tl.g(e));
+      if constexpr (HESS) xk[e] = ld<double>(A.xk, Tl.g(e));
+    }
+    if constexpr (EPI) Tl.pot_load(P, vp);
+  };
+#pragma unroll
+  for (int e = 0; e < E; ++e) u[e] = ld<T>(A.in, Tl.g(e));
+  if (Tl.sine) {       // odd extension: signs +1, -1 and zeros
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = (T)Tl.sgn(e) * u[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = u[e];
   }
-  if constexpr (EPI) Tl.pot_load(P, vp);
+  if constexpr (LOADS_AT == 0) late_loads();
   twf.store(lds);
-  spectral_apply<N, T>(P, ax, Tl, v, lds);
+  spectral_forward<N, T>(P, ax, Tl, v, lds);
+  spectral_inverse<N, T>(Tl, v, lds);
+  if constexpr (LOADS_AT == 2) late_loads();
   if constexpr (ROLE == R_FIRST) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -38,50 +59,51 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
 #pragma unroll
     for (int e = 0; e < E; ++e)
       if (Tl.inner(e)) stc<T>(P.t, Tl.g(e), tv[e] + v[e]);
-  } else {
-    double acc[SA_COUNT] = {};
+  } else if constexpr (HESS) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
       if (Tl.inner(e)) {
-        const int64_t g = Tl.g(e);
         cx<double> kin = cvt<double>(v[e]);
         if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
         const cx<double> uu = cvt<double>(u[e]);
         const double vg = Tl.pot_value(P, vp[e]);
-        const double q = abs2(uu);
-        if (A.kind == 0) {
-          const cx<double> h = kin + vg * uu + (P.beta * q) * uu;
-          stc<T>(A.out, g, cvt<T>(h));
-          acc[SA_KIN] += redot(uu, kin);
-          acc[SA_POT] += vg * q;
-          acc[SA_QUART] += q * q;
-          acc[SA_NORM] += q;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            if (a >= P.dim) break;
-            const int ca = a == 0 ? Tl.c0 : (a == 1 ? Tl.c1 : Tl.c2);
-            const int ia = a == ax ? Tl.idx(e) : ca;
-            const double xa = P.x0[a] + P.h[a] * (double)ia;   // a is a compile-time index here
-            acc[SA_X2 + a] += xa * xa * q;
-          }
-          acc[SA_MAXD] = fmax(acc[SA_MAXD], q);
-        } else {
-          const cx<double> x0 = xk[e];
-          const cx<double> hs = 2.0 * (kin + vg * uu) +
-                                (4.0 * P.alpha) * (abs2(x0) * uu + (2.0 * redot(x0, uu)) * x0) + A.delta * uu;
-          stc<T>(A.out, g, cvt<T>(hs));
-        }
+        const cx<double> x0 = xk[e];
+        const cx<double> hs = 2.0 * (kin + vg * uu) +
+                              (4.0 * P.alpha) * (abs2(x0) * uu + (2.0 * redot(x0, uu)) * x0) + A.delta * uu;
+        stc<T>(A.out, Tl.g(e), cvt<T>(hs));
       }
-    block_reduce<SA_COUNT_SUM, 1>(acc, red);
-    if (threadIdx.x == 0) {
-      const int64_t nt = pick3(P.tiles, P.dim - 1);
+  } else {
+    // H(phi) phi pointwise in the pass precision; the products entering
+    // mu = h_vol sum Re(conj(phi) H phi), sum |phi|^4 and sum V |phi|^2
+    // accumulate in FP64 (the other scalars come from the residual pass)
+    double acc[SA_COUNT] = {};
 #pragma unroll
-      for (int i = 0; i < SA_COUNT; ++i) gst<double>(P.partF, i * nt + tile, acc[i]);
+    for (int e = 0; e < E; ++e)
+      if (Tl.inner(e)) {
+        cx<T> kin = v[e];
+        if constexpr (HAS_T) kin = kin + tv[e];
+        const cx<T> uu = u[e];
+        const T vg = (T)Tl.pot_value(P, vp[e]);
+        const T q = uu.re * uu.re + uu.im * uu.im;
+        const cx<T> h = kin + (vg + (T)P.beta * q) * uu;
+        stc<T>(A.out, Tl.g(e), h);
+        acc[SA_MU] += (double)(uu.re * h.re + uu.im * h.im);
+        acc[SA_QUART] += (double)(q * q);
+        acc[SA_POT] += (double)(vg * q);
+      }
+    // one partial per wavefront (no workgroup barrier): entry tile * nw + wave
+    wave_reduce_k<SA_COUNT>(acc, 0u);
+    if ((threadIdx.x & 63) == 0) {
+      const int nw = blockDim.x >> 6;
+      const int64_t cnt = (int64_t)pick3(P.tiles, P.dim - 1) * nw;
+      const int64_t at = (int64_t)tile * nw + (threadIdx.x >> 6);
+#pragma unroll
+      for (int i = 0; i < SA_COUNT; ++i) gst<double>(P.partF, i * cnt + at, acc[i]);
     }
   }
 }
 
-template <int ROLE, typename T>
+template <int ROLE, typename T, int KIND>
 __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ probs, ApplyArgs A,
                                                     const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) char smem[];
@@ -91,13 +113,13 @@ __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ 
   const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   switch (n) {
-    case 16: apply_tile<16, ROLE, T>(P, A, tile, lds, tw, red); break;
-    case 32: apply_tile<32, ROLE, T>(P, A, tile, lds, tw, red); break;
-    case 64: apply_tile<64, ROLE, T>(P, A, tile, lds, tw, red); break;
-    case 128: apply_tile<128, ROLE, T>(P, A, tile, lds, tw, red); break;
-    case 256: apply_tile<256, ROLE, T>(P, A, tile, lds, tw, red); break;
-    case 512: apply_tile<512, ROLE, T>(P, A, tile, lds, tw, red); break;
-    case 1024: apply_tile<1024, ROLE, T>(P, A, tile, lds, tw, red); break;
+    case 16: apply_tile<16, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    case 32: apply_tile<32, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    case 64: apply_tile<64, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    case 128: apply_tile<128, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    case 256: apply_tile<256, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    case 512: apply_tile<512, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    case 1024: apply_tile<1024, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
     default: break;
   }
 }

@@ -17,11 +17,13 @@ void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64);
 void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
                       int prec64);
-// the energy sums into out[0, 1, 3..9], then per-block residual maxima (rpart)
-void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const void* phi, const void* hphi,
-                        double* rpart, double* out, int fp64);
-// out[2] = sqrt of the largest rpart entry
-void launch_apply_finalize(hipStream_t s, const double* rpart, int nr, double* out);
+// the last pass's nsum partials per slot into tot[SA_COUNT], then
+// per-block residual maxima (rpart) with mu from those totals
+void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, int nsum, const void* phi,
+                        const void* hphi, double* rpart, double* tot, int fp64);
+// out[0..9]: the scalars of gpe_apply_h from tot and the residual maxima
+void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* tot, const double* rpart, int nr,
+                           double* out);
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
                     double* part, double* coeffs);
 // per-block max |Im x_i| of a complex128 array (part[nblk])

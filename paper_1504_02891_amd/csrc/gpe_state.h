@@ -28,11 +28,12 @@ enum SlotF {
   SF_SMAX = SF_COUNT_SUM,  // max |S_j|
   SF_COUNT
 };
-// Reduction slots of apply_h (phi units).
-enum SlotA {
-  SA_KIN = 0, SA_POT, SA_QUART, SA_NORM, SA_X2, SA_Y2, SA_Z2, SA_COUNT_SUM,
-  SA_MAXD = SA_COUNT_SUM, SA_COUNT
-};
+// Reduction slots of apply_h (phi units): sums of the last pass, sum
+// Re(conj(phi) H phi), sum |phi|^4, sum V |phi|^2 ...
+enum SlotA { SA_MU = 0, SA_QUART, SA_POT, SA_COUNT };
+// ... and of the residual pass: norm, second moments, then the maxima of
+// |phi|^2 and |H phi - mu phi|^2.
+enum SlotR { SR_NORM = 0, SR_X2, SR_Y2, SR_Z2, SR_COUNT_SUM, SR_MAXD = SR_COUNT_SUM, SR_RES, SR_COUNT };
 
 // Roles of the directional passes of one evaluation.
 enum Role { R_FIRST = 0, R_MID = 1, R_FINAL = 2, R_SOLO = 3 };

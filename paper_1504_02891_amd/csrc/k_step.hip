@@ -58,7 +58,8 @@ constexpr int kSumThreads = 1024;
 template <int NS, int NM>
 __device__ __forceinline__ void block_sum_partials(const double* part, int count, double* acc, double* red) {
   constexpr int NSLOT = NS + NM;
-  constexpr int B = NSLOT >= 4 ? 4 : 8;     // loads in flight per slot (128 registers at 1024 threads)
+  // loads in flight per slot per thread (at most 128 registers at 1024 threads)
+  constexpr int B = NSLOT >= 4 ? 4 : 8;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;
   for (int b0 = 0; b0 < count; b0 += B * kSumThreads) {
@@ -78,50 +79,107 @@ __device__ __forceinline__ void block_sum_partials(const double* part, int count
   block_reduce<NS, NM>(acc, red);
 }
 
-// The energy sums of the last pass: out[0] = E, out[1] = mu, out[3..9] as
-// documented for gpe_apply_h (out[2], the residual, comes from the last kernel)
-__global__ void __launch_bounds__(kSumThreads) k_apply_sums(const ProbDev* probs, double* __restrict__ out) {
-  __shared__ double red[SA_COUNT * 16];
+// Totals of the last pass's `count` partials per slot (one per wavefront):
+// workgroup s sums slot s into tot[s].
+__global__ void __launch_bounds__(kSumThreads) k_apply_sums(const ProbDev* probs, int count,
+                                                            double* __restrict__ tot) {
+  __shared__ double red[16];
   const ProbDev& P = probs[0];
-  double acc[SA_COUNT];
-  block_sum_partials<SA_COUNT_SUM, 1>(P.partF, pick3(P.tiles, P.dim - 1), acc, red);
-  if (threadIdx.x == 0) {
-    const double e = P.hvol * (acc[SA_KIN] + acc[SA_POT] + 0.5 * P.beta * acc[SA_QUART]);
-    out[0] = e;
-    out[1] = e + 0.5 * P.beta * P.hvol * acc[SA_QUART];
-    out[3] = P.hvol * acc[SA_NORM];
-    out[4] = sqrt(P.hvol * acc[SA_X2]);
-    out[5] = sqrt(P.hvol * acc[SA_Y2]);
-    out[6] = sqrt(P.hvol * acc[SA_Z2]);
-    out[7] = acc[SA_MAXD];
-    out[8] = P.hvol * acc[SA_KIN];
-    out[9] = P.hvol * acc[SA_POT];
-  }
+  const int slot = blockIdx.x;
+  const double* part = P.partF + (int64_t)slot * count;
+  double acc[1];
+  block_sum_partials<1, 0>(part, count, acc, red);
+  if (threadIdx.x == 0) tot[slot] = acc[0];
 }
 
+// E and mu from the last pass's totals: mu = h_vol sum Re(conj(phi) H phi),
+// E = mu - beta/2 h_vol sum |phi|^4 (§1: mu = E + beta/2 int |phi|^4)
+__device__ __forceinline__ double apply_mu(const ProbDev& P, const double* tot) {
+  return P.hvol * tot[SA_MU];
+}
+__device__ __forceinline__ double apply_energy(const ProbDev& P, const double* tot) {
+  return apply_mu(P, tot) - 0.5 * P.beta * P.hvol * tot[SA_QUART];
+}
+
+// q = a / d and a - q d for a < 2^31, d >= 1, rd = 1/d rounded: the FP64
+// quotient a * rd is within 2^-21 of a / d, so one correction step suffices.
+__device__ __forceinline__ uint32_t div_rcp(uint32_t a, uint32_t d, double rd, uint32_t& rem) {
+  uint32_t q = (uint32_t)((double)a * rd);
+  int32_t r = (int32_t)(a - q * d);
+  if (r < 0) { q -= 1; r += (int32_t)d; }
+  else if (r >= (int32_t)d) { q += 1; r -= (int32_t)d; }
+  rem = (uint32_t)r;
+  return q;
+}
+
+// Residual pass: per block, sums of |phi|^2 and x_a^2 |phi|^2 and the maxima
+// of |phi|^2 and |H phi - mu phi|^2 (rpart slot-major, [SR_COUNT][gridDim]).
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply_resid(const ProbDev* probs, const cx<T>* __restrict__ phi,
-                                                     const cx<T>* __restrict__ hphi, const double* __restrict__ out,
+                                                     const cx<T>* __restrict__ hphi, const double* __restrict__ tot,
                                                      double* __restrict__ rpart) {
-  __shared__ double red[16];
+  __shared__ double red[SR_COUNT * 16];
   const ProbDev& P = probs[0];
-  const double mu = out[1];
-  double r = 0.0;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
-    const cx<double> u = cvt<double>(phi[g]), h = cvt<double>(hphi[g]);
-    r = fmax(r, abs2(h - mu * u));
+  const double mu = apply_mu(P, tot);
+  const uint32_t n0 = (uint32_t)P.n[0], n1 = (uint32_t)P.n[1];
+  const double r0 = 1.0 / (double)n0, r1 = 1.0 / (double)n1;
+  double acc[SR_COUNT] = {};
+  auto point = [&](int64_t g, cx<T> pu, cx<T> ph) {
+    const cx<double> u = cvt<double>(pu), h = cvt<double>(ph);
+    const double q = abs2(u);
+    uint32_t i0, i1;
+    const uint32_t i2 = div_rcp(div_rcp((uint32_t)g, n0, r0, i0), n1, r1, i1);
+    const double x = P.x0[0] + P.h[0] * (double)i0, y = P.x0[1] + P.h[1] * (double)i1,
+                 z = P.x0[2] + P.h[2] * (double)i2;
+    acc[SR_NORM] += q;
+    acc[SR_X2] += x * x * q;
+    acc[SR_Y2] += y * y * q;
+    acc[SR_Z2] += z * z * q;
+    acc[SR_MAXD] = fmax(acc[SR_MAXD], q);
+    acc[SR_RES] = fmax(acc[SR_RES], abs2(h - mu * u));
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  constexpr int U = sizeof(T) == 4 ? 4 : 1;     // points whose loads are in flight together
+  for (; g + (U - 1) * stride < P.m; g += U * stride) {
+    cx<T> u[U], h[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      u[k] = phi[g + k * stride];
+      h[k] = hphi[g + k * stride];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) point(g + k * stride, u[k], h[k]);
   }
-  double acc[1] = {r};
-  block_reduce<0, 1>(acc, red);
-  if (threadIdx.x == 0) rpart[blockIdx.x] = acc[0];
+  for (; g < P.m; g += stride) point(g, phi[g], hphi[g]);
+  block_reduce<SR_COUNT_SUM, 2>(acc, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int s = 0; s < SR_COUNT; ++s) rpart[(int64_t)s * gridDim.x + blockIdx.x] = acc[s];
 }
 
-__global__ void __launch_bounds__(kSumThreads) k_apply_finalize(const double* __restrict__ rpart, int nr,
+// The scalars documented for gpe_apply_h: out[0] = E, out[1] = mu, out[2] the
+// residual, out[3..9] norm, rms, max density, energy parts.
+__global__ void __launch_bounds__(kSumThreads) k_apply_finalize(const ProbDev* probs, const double* __restrict__ tot,
+                                                                const double* __restrict__ rpart, int nr,
                                                                 double* __restrict__ out) {
-  __shared__ double red[16];
-  double acc[1];
-  block_sum_partials<0, 1>(rpart, nr, acc, red);
-  if (threadIdx.x == 0) out[2] = sqrt(acc[0]);
+  __shared__ double red[SR_COUNT * 16];
+  const ProbDev& P = probs[0];
+  double acc[SR_COUNT];
+  block_sum_partials<SR_COUNT_SUM, 2>(rpart, nr, acc, red);
+  if (threadIdx.x == 0) {
+    const double e = apply_energy(P, tot), epot = P.hvol * tot[SA_POT];
+    out[0] = e;
+    out[1] = apply_mu(P, tot);
+    out[2] = sqrt(acc[SR_RES]);
+    out[3] = P.hvol * acc[SR_NORM];
+    out[4] = sqrt(P.hvol * acc[SR_X2]);
+    out[5] = sqrt(P.hvol * acc[SR_Y2]);
+    out[6] = sqrt(P.hvol * acc[SR_Z2]);
+    out[7] = acc[SR_MAXD];
+    out[8] = e - epot - 0.5 * P.beta * P.hvol * tot[SA_QUART];
+    out[9] = epot;
+  }
 }
 
 // ---- largest |Im| of the initial data (choice of real arithmetic) ----
@@ -233,16 +291,17 @@ void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st
   if (prec64) hipLaunchKernelGGL(k_write_phi<double>, dim3(blocks), dim3(256), 0, s, probs, st, pi, (cx<double>*)phi);
   else hipLaunchKernelGGL(k_write_phi<float>, dim3(blocks), dim3(256), 0, s, probs, st, pi, (cx<double>*)phi);
 }
-void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, const void* phi, const void* hphi,
-                        double* rpart, double* out, int fp64) {
-  hipLaunchKernelGGL(k_apply_sums, dim3(1), dim3(kSumThreads), 0, s, probs, out);
+void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, int nsum, const void* phi,
+                        const void* hphi, double* rpart, double* tot, int fp64) {
+  hipLaunchKernelGGL(k_apply_sums, dim3(SA_COUNT), dim3(kSumThreads), 0, s, probs, nsum, tot);
   if (fp64) hipLaunchKernelGGL(k_apply_resid<double>, dim3(nblk), dim3(256), 0, s, probs,
-                               (const cx<double>*)phi, (const cx<double>*)hphi, (const double*)out, rpart);
+                               (const cx<double>*)phi, (const cx<double>*)hphi, (const double*)tot, rpart);
   else hipLaunchKernelGGL(k_apply_resid<float>, dim3(nblk), dim3(256), 0, s, probs,
-                          (const cx<float>*)phi, (const cx<float>*)hphi, (const double*)out, rpart);
+                          (const cx<float>*)phi, (const cx<float>*)hphi, (const double*)tot, rpart);
 }
-void launch_apply_finalize(hipStream_t s, const double* rpart, int nr, double* out) {
-  hipLaunchKernelGGL(k_apply_finalize, dim3(1), dim3(kSumThreads), 0, s, rpart, nr, out);
+void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* tot, const double* rpart, int nr,
+                           double* out) {
+  hipLaunchKernelGGL(k_apply_finalize, dim3(1), dim3(kSumThreads), 0, s, probs, tot, rpart, nr, out);
 }
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
                     double* part, double* coeffs) {

@@ -119,14 +119,13 @@ __device__ __forceinline__ CT axis_mult(int k, int n, CT two_pi_over_len, CT rc,
   return ((CT)0.5 * lam * lam + rc * lam) * inv_n;
 }
 
-// Forward transform, multiplier, inverse transform of the tile's lines.
-// `lds` holds the twiddle table (N entries) followed by the line data.
+// Forward transform and multiplier (spectral_forward), inverse transform
+// (spectral_inverse) of the tile's lines; spectral_apply is both.  `lds`
+// holds the twiddle table (N entries) followed by the line data.
 template <int N, typename CT>
-__device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
-                                               cx<CT>* lds) {
-  const cx<CT>* twl = lds;
-  cx<CT>* data = lds + N;
-  line_fft<N, false>(v, T.t, T.lane, T.mp, data, twl);
+__device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
+                                                 cx<CT>* lds) {
+  line_fft<N, false>(v, T.t, T.lane, T.mp, lds + N, lds);
   const CT rc = (CT)T.rot(P);
   const CT tpl = (CT)(6.283185307179586477 / pick3(P.len, ax));
   const CT inv_n = (CT)1 / (CT)N;
@@ -135,7 +134,16 @@ __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const T
     const CT mlt = axis_mult<CT>(T.t + e * Tile<N>::TL, N, tpl, rc, inv_n);
     v[e] = mlt * v[e];
   }
-  line_fft<N, true>(v, T.t, T.lane, T.mp, data, twl);
+}
+template <int N, typename CT>
+__device__ __forceinline__ void spectral_inverse(const Tile<N>& T, cx<CT>* v, cx<CT>* lds) {
+  line_fft<N, true>(v, T.t, T.lane, T.mp, lds + N, lds);
+}
+template <int N, typename CT>
+__device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
+                                               cx<CT>* lds) {
+  spectral_forward<N, CT>(P, ax, T, v, lds);
+  spectral_inverse<N, CT>(T, v, lds);
 }
 
 // One slot of the fixed-order reduction (the same bits as that slot of the

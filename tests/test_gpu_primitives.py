@@ -119,6 +119,31 @@ def test_apply_h_explicit_potential_array(dev):
     assert float(np.max(np.abs(out.cpu().numpy() - ref))) <= _bound(q, phi, "fp64")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_apply_h_without_readback(dev, prec):
+    # calls without scalars only enqueue work; switching problems between
+    # them must still upload each problem's descriptor and V tables
+    pa, pb = CASES[6], W.Problem(dim=3, n=(32, 16, 64), lo=(-5.0, -5.0, -9.0), hi=(5.0, 5.0, 9.0),
+                                 beta=40.0, omega=-0.2, gamma=(2.0, 1.0, 0.5), lattice_amp=3.0)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    ta = torch.from_numpy(_field(pa, 11)).to(dt).cuda()
+    tb = torch.from_numpy(_field(pb, 12)).to(dt).cuda()
+    ref_a, _ = dev.apply_h(pa, ta, precision=prec)
+    ref_b, _ = dev.apply_h(pb, tb, precision=prec)
+    outs = []
+    for q, t in ((pa, ta), (pa, ta), (pb, tb), (pa, ta), (pb, tb), (pb, tb)):
+        o, sc = dev.apply_h(q, t, precision=prec, scalars=False)
+        assert sc is None
+        outs.append(o)
+    torch.cuda.synchronize()
+    for o, ref in zip(outs, (ref_a, ref_a, ref_b, ref_a, ref_b, ref_b)):
+        assert torch.equal(o, ref)
+    # and the scalars of a later synchronous call are those of its own problem
+    _, sa = dev.apply_h(pa, ta, precision=prec)
+    o = UnifiedProblem(pa).outputs(UnifiedProblem(pa).to_x(ta.cpu().numpy().astype(np.complex128)))
+    assert abs(sa["energy"] - o["energy"]) <= (1e-11 if prec == "fp64" else 3e-6) * abs(o["energy"])
+
+
 @pytest.mark.parametrize("p", [CASES[1], CASES[3], CASES[6]], ids=_cid)
 def test_hess_vec_matches_oracle(dev, p):
     up = UnifiedProblem(p)
