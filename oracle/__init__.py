@@ -6,8 +6,8 @@ GPU library never calls into this package and shares no code with it.
 
 Plain, slow, obviously-correct NumPy/SciPy code in float64 / complex128:
 
-* ``discretization`` -- grid, trap, Fourier and sine pseudospectral
-  operators (§2.2, §2.3).
+* ``discretization`` -- grid, trap, Fourier and sine pseudospectral and
+  finite-difference operators (§2.1, §2.2, §2.3).
 * ``unified``        -- the unified problem F(X) on the unit sphere, its
   gradient and Hessian (§3, Lemma 3.1), chemical potential and residual.
 * ``feasible``       -- the Cayley curve (Theorem 3.3) and the feasible

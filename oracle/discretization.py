@@ -18,22 +18,27 @@ Sine pseudospectral (§2.2, homogeneous Dirichlet, Omega = 0): per axis the
 kinetic part is (1/N) C Lambda C with c_jl = sin(j l pi / N) and
 Lambda = diag(lambda_l^2), lambda_l = pi l / (b - a), on interior points.
 scipy's DST-I computes 2 C x, hence (1/N) C Lambda C x = dst1(Lambda dst1(x))/(4N).
+
+Finite differences (§2.1, homogeneous Dirichlet, Omega = 0): on the interior
+points the kinetic part is the symmetric tridiagonal matrix with 1/h^2 on the
+diagonal and -1/(2 h^2) beside it, i.e. -1/2 (phi_{j+1} - 2 phi_j + phi_{j-1})/h^2
+with phi_0 = phi_N = 0, applied along every axis (the paper's A minus V).
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.fft as sfft
 
-from workloads import FOURIER, SINE
+from workloads import FOURIER, SINE, FD, DIRICHLET
 
 
 def axis_points(p, ax):
     """Grid points on axis ``ax``: x_j = a + j h, h = (b-a)/N.
 
-    Fourier: j = 0..N-1 (unique periodic points, §2.3).
-    Sine:    j = 1..N-1 (interior points, §2.2)."""
+    Fourier:  j = 0..N-1 (unique periodic points, §2.3).
+    Sine, FD: j = 1..N-1 (interior points, §2.2, §2.1)."""
     h = (p.hi[ax] - p.lo[ax]) / p.n[ax]
-    j = np.arange(1, p.n[ax]) if p.bc == SINE else np.arange(p.n[ax])
+    j = np.arange(1, p.n[ax]) if p.bc in DIRICHLET else np.arange(p.n[ax])
     return p.lo[ax] + j * h
 
 
@@ -106,8 +111,30 @@ def _kinetic_sine(p, phi):
     return out
 
 
+def _kinetic_fd(p, phi):
+    d = p.dim
+    out = np.zeros(phi.shape, dtype=phi.dtype)
+    for ax in range(d):
+        npax = d - 1 - ax
+        h = (p.hi[ax] - p.lo[ax]) / p.n[ax]
+        # the boundary values phi_0 = phi_N = 0 as explicit zeros
+        pad = [(0, 0)] * d
+        pad[npax] = (1, 1)
+        q = np.pad(phi, pad)
+        sl = lambda a, b: tuple(slice(a, b) if k == npax else slice(None) for k in range(d))
+        m = phi.shape[npax]
+        lap = (q[sl(2, m + 2)] - 2.0 * q[sl(1, m + 1)] + q[sl(0, m)]) / (h * h)
+        out = out - 0.5 * lap
+    return out
+
+
 def kinetic(p, phi):
     """Kinetic (+ rotation) part of H_lin: everything but V."""
+    if p.bc == FD:
+        if p.omega != 0.0:
+            raise ValueError("the finite-difference discretization here needs Omega = 0")
+        phi = np.asarray(phi)
+        return _kinetic_fd(p, phi.astype(np.complex128 if np.iscomplexobj(phi) else np.float64))
     if p.bc == SINE:
         if p.omega != 0.0:
             raise ValueError("sine pseudospectral discretization needs Omega = 0")

@@ -42,7 +42,7 @@ class UnifiedProblem:
         self.alpha = p.beta / (2.0 * self.hvol)
         self.v = disc.potential(p)
         self.coords = disc.grid_coords(p)
-        self.dtype = np.float64 if p.bc == "sine" else np.complex128
+        self.dtype = np.float64 if p.bc in ("sine", "fd") else np.complex128
 
     # -- the linear operator A = 2 H_lin ---------------------------------
     def A(self, x):

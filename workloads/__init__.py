@@ -7,8 +7,9 @@ paper lists for its experiments, sampled on the grid with seeded noise.
 
 Grid convention (Fourier pseudospectral, §2.3): ``n`` unique periodic points
 per axis, ``x_j = lo + j*h``, ``h = (hi-lo)/n``, ``j = 0..n-1`` (the paper's
-"2^k+1 nodes" with the periodic copy dropped).  Sine pseudospectral (§2.2):
-``n`` intervals, interior points ``j = 1..n-1``.  Arrays are numpy arrays in
+"2^k+1 nodes" with the periodic copy dropped).  Sine pseudospectral (§2.2)
+and finite differences (§2.1), both homogeneous Dirichlet: ``n`` intervals,
+interior points ``j = 1..n-1``.  Arrays are numpy arrays in
 C order with x fastest: shape ``(nx,)``, ``(ny, nx)`` or ``(nz, ny, nx)``.
 """
 from __future__ import annotations
@@ -21,6 +22,8 @@ import numpy as np
 
 FOURIER = "fourier"
 SINE = "sine"
+FD = "fd"
+DIRICHLET = (SINE, FD)      # grids of interior points
 
 
 @dataclasses.dataclass
@@ -30,7 +33,7 @@ class Problem:
     dim          spatial dimension d (1, 2, 3)
     n            points per axis (x, y, z order); see the module docstring
     lo, hi       computational box U = prod (lo_i, hi_i)
-    bc           FOURIER (periodic) or SINE (homogeneous Dirichlet)
+    bc           FOURIER (periodic), SINE or FD (homogeneous Dirichlet)
     beta         interaction constant
     omega        rotation speed (0 unless FOURIER and dim >= 2)
     gamma        harmonic trap frequencies, V = 1/2 sum gamma_i^2 x_i^2
@@ -61,7 +64,7 @@ class Problem:
     @property
     def shape(self):
         """numpy shape, x fastest."""
-        if self.bc == SINE:
+        if self.bc in DIRICHLET:
             return tuple(n - 1 for n in reversed(self.n))
         return tuple(reversed(self.n))
 
@@ -75,7 +78,7 @@ class Problem:
 
 def _axis_points(p: Problem, axis: int) -> np.ndarray:
     h = (p.hi[axis] - p.lo[axis]) / p.n[axis]
-    if p.bc == SINE:
+    if p.bc in DIRICHLET:
         j = np.arange(1, p.n[axis])
     else:
         j = np.arange(p.n[axis])
