@@ -48,6 +48,9 @@ extern "C" {
 #define GPE_BC_FOURIER       0   /* periodic, Fourier pseudospectral (§2.3) */
 #define GPE_BC_SINE          1   /* homogeneous Dirichlet, sine pseudospectral (§2.2, DST-I);
                                     Omega must be 0 */
+#define GPE_BC_FD            2   /* homogeneous Dirichlet, second-order finite differences (§2.1):
+                                    per axis the tridiagonal 1/h^2, -1/(2h^2) kinetic matrix on the
+                                    n-1 interior points; Omega must be 0 */
 
 #define GPE_PREC_FP64        0   /* every array and FFT in float64 */
 #define GPE_PREC_MIXED       1   /* FP32 FFT/pointwise bulk, FP64 reductions, scalars and outer Newton state */
@@ -127,8 +130,10 @@ typedef struct gpe_options {
     double eps0;          /* GPE_STOP_CRIT1 threshold (1e-6, §4) */
     double crit2_tol;     /* GPE_STOP_CRIT2 threshold delta_0 (1e-8, §4) */
     int32_t switch_window;/* mixed precision, Algorithm 1: when the residual has not halved in
-                             this many accepted steps (the FP32 floor), continue from the current
-                             iterate in FP64 with the remaining steps; 0 = never (default 100) */
+                             this many accepted steps (the FP32 floor), or when an FP32 residual
+                             meets tol, continue from the current iterate in FP64 with the
+                             remaining steps (the stop test is then taken in FP64); 0 = never:
+                             the FP32 residual decides (default 100) */
     int32_t reserved1;
 } gpe_options;
 

@@ -20,6 +20,7 @@ GPE_ENONFINITE = -5
 
 GPE_BC_FOURIER = 0
 GPE_BC_SINE = 1
+GPE_BC_FD = 2
 GPE_PREC_FP64 = 0
 GPE_PREC_MIXED = 1
 GPE_ALG1 = 1

@@ -52,7 +52,7 @@ def problem_struct(p, v=None):
     ``v``: optional CUDA float64 tensor with the potential on the grid."""
     s = N.Problem()
     s.dim = int(p.dim)
-    s.bc = {"fourier": N.GPE_BC_FOURIER, "sine": N.GPE_BC_SINE}[getattr(p, "bc", "fourier")]
+    s.bc = {"fourier": N.GPE_BC_FOURIER, "sine": N.GPE_BC_SINE, "fd": N.GPE_BC_FD}[getattr(p, "bc", "fourier")]
     for i in range(3):
         s.n[i] = int(p.n[i]) if i < p.dim else 1
         s.lo[i] = float(p.lo[i]) if i < p.dim else 0.0
@@ -108,11 +108,12 @@ def _dev_tensor(t, dtype, name, p=None):
 
 def grid_points(p):
     """Number of grid values of a problem (the library reads exactly this many):
-    n per axis (Fourier) or n - 1 interior points per axis (sine)."""
-    sine = getattr(p, "bc", "fourier") == "sine"
+    n per axis (Fourier) or n - 1 interior points per axis (sine, finite
+    differences)."""
+    dirichlet = getattr(p, "bc", "fourier") in ("sine", "fd")
     m = 1
     for i in range(int(p.dim)):
-        m *= int(p.n[i]) - (1 if sine else 0)
+        m *= int(p.n[i]) - (1 if dirichlet else 0)
     return m
 
 

@@ -144,26 +144,28 @@ bool pow2_ok(int n) { return n >= 16 && n <= kMaxN && (n & (n - 1)) == 0; }
 int build_prob(const gpe_problem* p, ProbDev* d, double* vaxis) {
   if (!p || !d) return GPE_EINVAL;
   if (p->dim < 1 || p->dim > 3) return GPE_EINVAL;
-  if (p->bc != GPE_BC_FOURIER && p->bc != GPE_BC_SINE) return GPE_EINVAL;
-  const bool sine = p->bc == GPE_BC_SINE;
+  if (p->bc != GPE_BC_FOURIER && p->bc != GPE_BC_SINE && p->bc != GPE_BC_FD) return GPE_EINVAL;
+  const bool sine = p->bc == GPE_BC_SINE, fd = p->bc == GPE_BC_FD, dirichlet = sine || fd;
   if (!std::isfinite(p->beta) || !std::isfinite(p->omega)) return GPE_EINVAL;
-  if ((p->dim == 1 || sine) && p->omega != 0.0) return GPE_EINVAL;
+  if ((p->dim == 1 || dirichlet) && p->omega != 0.0) return GPE_EINVAL;
   std::memset(d, 0, sizeof(*d));
   d->dim = p->dim;
-  d->bc = sine ? BC_SINE : BC_FOURIER;
+  d->bc = sine ? BC_SINE : (fd ? BC_FD : BC_FOURIER);
   d->m = 1;
   double hvol = 1.0;
   for (int i = 0; i < 3; ++i) {
     if (i < p->dim) {
-      // sine: n intervals, n-1 interior points, transform of the 2n-point odd extension
+      // sine: n intervals, n-1 interior points, transform of the 2n-point odd
+      // extension; finite differences: n-1 interior points on lines of n
+      // positions (position 0 the boundary)
       if (!pow2_ok(p->n[i]) || (sine && 2 * p->n[i] > kMaxN)) return GPE_EUNSUPPORTED;
       if (!(p->lo[i] < p->hi[i]) || !std::isfinite(p->lo[i]) || !std::isfinite(p->hi[i])) return GPE_EINVAL;
       const double box = p->hi[i] - p->lo[i];
-      d->n[i] = sine ? p->n[i] - 1 : p->n[i];
+      d->n[i] = dirichlet ? p->n[i] - 1 : p->n[i];
       d->nl[i] = sine ? 2 * p->n[i] : p->n[i];
       d->lo[i] = p->lo[i];
       d->h[i] = box / p->n[i];
-      d->x0[i] = sine ? p->lo[i] + d->h[i] : p->lo[i];
+      d->x0[i] = dirichlet ? p->lo[i] + d->h[i] : p->lo[i];
       d->len[i] = sine ? 2.0 * box : box;
       hvol *= d->h[i];
     } else {

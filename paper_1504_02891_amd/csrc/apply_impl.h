@@ -39,7 +39,7 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
   };
 #pragma unroll
   for (int e = 0; e < E; ++e) u[e] = ld<T>(A.in, Tl.g(e));
-  if (Tl.sine) {       // odd extension: signs +1, -1 and zeros
+  if (Tl.sine || Tl.fd) {   // odd extension: signs +1, -1 and zeros; FD: the boundary zero
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = (T)Tl.sgn(e) * u[e];
   } else {

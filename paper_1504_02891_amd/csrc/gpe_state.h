@@ -56,18 +56,20 @@ enum StopRule : int32_t { STOP_RESID = 0, STOP_CRIT1 = 1, STOP_CRIT2 = 2 };
 enum OuterSrc : int32_t { SRC_XK = 0, SRC_XK_PLUS_S = 1, SRC_XF = 2 };
 
 // Boundary treatment of a problem (the GPE_BC_* values).
-enum Bc : int32_t { BC_FOURIER = 0, BC_SINE = 1 };
+enum Bc : int32_t { BC_FOURIER = 0, BC_SINE = 1, BC_FD = 2 };
 
 // Per-problem description used on the device (read only in kernels).
 // Fourier: n[a] periodic points, each line transformed as it is.  Sine:
 // n[a] = N-1 interior points of N intervals; each line is transformed as its
 // odd extension of nl[a] = 2N points (zero at 0 and N, mirrored with a sign
 // change above N), which turns the Fourier multiplier into the sine
-// operator's.
+// operator's.  Finite differences: n[a] = N-1 interior points held at line
+// positions 1..N-1 of a line of nl[a] = N points whose position 0 is the
+// boundary value 0 (the other boundary value sits past the line's end).
 struct ProbDev {
   int32_t dim;
   int32_t n[3];          // array points per axis
-  int32_t nl[3];         // transform length per axis: n (Fourier) or 2(n+1) (sine)
+  int32_t nl[3];         // line length per axis: n (Fourier), 2(n+1) (sine), n+1 (finite differences)
   int32_t bc;            // Bc
   int64_t stride[3];     // element stride of each axis: 1, nx, nx*ny
   int64_t m;             // number of grid points
@@ -78,7 +80,7 @@ struct ProbDev {
   int32_t real;          // 1: drop the imaginary parts of every stored iterate and gradient
   int32_t pad_r;
   double lo[3], h[3], len[3];   // len: period of the transformed line (b-a, or 2(b-a) for sine)
-  double x0[3];          // coordinate of array index 0 (lo, or lo + h for sine)
+  double x0[3];          // coordinate of array index 0 (lo, or lo + h for sine and finite differences)
   double beta, omega, hvol, sqrt_hvol, alpha;
   const double* v_arr;   // explicit V (float64), or null
   const double* v_axis;  // [3][kMaxN]: V = v_axis[0][x] + v_axis[1][y] + v_axis[2][z]

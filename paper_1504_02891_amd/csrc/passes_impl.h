@@ -26,19 +26,22 @@ __device__ __forceinline__ int role_axis(int role, int dim) {
 // transform position p of the odd extension reads array index p-1 (p < N/2)
 // or N-1-p (p > N/2) with sign +1 / -1, and is zero at p = 0 and p = N/2;
 // only positions 1 .. N/2-1 ("inner") write results and enter reductions.
+// For finite differences position p reads array index p-1 and position 0
+// holds the boundary value 0; positions 1 .. N-1 are inner.
 // `P` is a local copy of the descriptor.
 template <int N>
 struct Tile {
   static constexpr int E = Plan<N>::E, TL = N / E;
   int lanes, lane, t, ax;
   int c0, c1, c2;    // array coordinates of the line's first point (x, y, z)
-  bool act, sine;
+  bool act, sine, fd;
   int64_t base, st;
   double va[3];      // separable V tables at the line's fixed coordinates
   LdsMap mp;
   __device__ __forceinline__ Tile(const ProbDev& P, int ax_, bool strided, int tile) {
     ax = ax_;
     sine = P.bc == BC_SINE;
+    fd = P.bc == BC_FD;
     lanes = blockDim.x / TL;
     if (strided) { lane = threadIdx.x % lanes; t = threadIdx.x / lanes; }
     else { lane = threadIdx.x / TL; t = threadIdx.x % TL; }
@@ -64,6 +67,7 @@ struct Tile {
   // array index along the axis of transform position pos(e)
   __device__ __forceinline__ int idx(int e) const {
     const int p = pos(e);
+    if (fd) return p > 0 ? p - 1 : 0;
     if (!sine) return p;
     const int h = N / 2;
     const int i = p < h ? p - 1 : N - 1 - p;
@@ -72,13 +76,14 @@ struct Tile {
   // sign of the odd extension at pos(e) (0 where it vanishes)
   __device__ __forceinline__ double sgn(int e) const {
     const int p = pos(e);
+    if (fd) return p > 0 ? 1.0 : 0.0;
     if (!sine) return 1.0;
     return (p == 0 || p == N / 2) ? 0.0 : (p < N / 2 ? 1.0 : -1.0);
   }
   // pos(e) holds an array point of this line (not a mirror image)
   __device__ __forceinline__ bool inner(int e) const {
     const int p = pos(e);
-    return act && (!sine || (p > 0 && p < N / 2));
+    return act && (fd ? p > 0 : (!sine || (p > 0 && p < N / 2)));
   }
   __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)idx(e) * st; }
   // Potential at the thread's elements in two steps, so that the loads join
@@ -119,12 +124,41 @@ __device__ __forceinline__ CT axis_mult(int k, int n, CT two_pi_over_len, CT rc,
   return ((CT)0.5 * lam * lam + rc * lam) * inv_n;
 }
 
+// Finite differences (§2.1): -1/2 (u_{p+1} - 2 u_p + u_{p-1}) / h^2 along
+// the line through the LDS line buffer; u at position 0 is the boundary
+// value 0 (the caller's sign factor), the value past position N-1 the other.
+template <int N, typename CT>
+__device__ __forceinline__ void fd_stencil(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
+                                           cx<CT>* lds) {
+  cx<CT>* data = lds + N;
+  __syncthreads();       // nobody still reads the LDS lines
+#pragma unroll
+  for (int e = 0; e < Tile<N>::E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
+  __syncthreads();
+  const double h = pick3(P.h, ax);
+  const CT c = (CT)(0.5 / (h * h));
+  const cx<CT> zero{(CT)0, (CT)0};
+#pragma unroll
+  for (int e = 0; e < Tile<N>::E; ++e) {
+    const int p = T.pos(e);
+    const cx<CT> lft = data[T.mp.idx(T.lane, p > 0 ? p - 1 : 0, N)];
+    const cx<CT> rgt = data[T.mp.idx(T.lane, p < N - 1 ? p + 1 : N - 1, N)];
+    const cx<CT> l = p > 0 ? lft : zero, r = p < N - 1 ? rgt : zero;
+    v[e] = c * (((CT)2 * v[e] - l) - r);
+  }
+}
+
 // Forward transform and multiplier (spectral_forward), inverse transform
 // (spectral_inverse) of the tile's lines; spectral_apply is both.  `lds`
-// holds the twiddle table (N entries) followed by the line data.
+// holds the twiddle table (N entries) followed by the line data.  Finite
+// differences apply their stencil in the forward half.
 template <int N, typename CT>
 __device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
                                                  cx<CT>* lds) {
+  if (T.fd) {
+    fd_stencil<N, CT>(P, ax, T, v, lds);
+    return;
+  }
   line_fft<N, false>(v, T.t, T.lane, T.mp, lds + N, lds);
   const CT rc = (CT)T.rot(P);
   const CT tpl = (CT)(6.283185307179586477 / pick3(P.len, ax));
@@ -137,7 +171,7 @@ __device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const
 }
 template <int N, typename CT>
 __device__ __forceinline__ void spectral_inverse(const Tile<N>& T, cx<CT>* v, cx<CT>* lds) {
-  line_fft<N, true>(v, T.t, T.lane, T.mp, lds + N, lds);
+  if (!T.fd) line_fft<N, true>(v, T.t, T.lane, T.mp, lds + N, lds);
 }
 template <int N, typename CT>
 __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,

@@ -112,7 +112,14 @@ __device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, con
     const double rb = sqrt(r1[S1_RMAX]) * rscale;   // residual of the base point (phi units)
     if (S.phase == PH_ALG1) {
       const bool resid_rule = S.stop_rule == STOP_RESID || (S.alg == 2 && S.stop_rule == STOP_CRIT2);
-      if (resid_rule && rb < S.tol) { end_alg1(S, true); return; }
+      if (resid_rule && rb < S.tol) {
+        // an FP32 residual carries the transforms' rounding: mixed-precision
+        // Algorithm 1 hands its iterate to the FP64 continuation, which tests
+        // (and if needed refines) it in FP64
+        if (!prec64 && S.alg == 1 && S.switch_window > 0) { finish(S, kStatusStalled, SRC_XF); return; }
+        end_alg1(S, true);
+        return;
+      }
       if (!prec64 && S.alg == 1 && S.switch_window > 0) {
         // FP32 floor: no halving of the best residual within the window
         if (rb < 0.5 * S.best_r) {

@@ -272,3 +272,86 @@ def test_apply_h_rotating_3d_eigenfunction(dev):
     out, _ = dev.apply_h(p, torch.from_numpy(np.ascontiguousarray(f)).cuda())
     lam = 2.0 - om + 0.5 * gz
     assert float(np.max(np.abs(out.cpu().numpy() - lam * f))) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Second-order finite differences (Dirichlet), §2.1: n intervals, n-1
+# interior points per axis, the tridiagonal kinetic matrix per axis.
+# ---------------------------------------------------------------------------
+FD_CASES = [
+    W.Problem(dim=1, n=(16,), lo=(-4.0,), hi=(4.0,), bc=W.FD, beta=10.0),
+    W.Problem(dim=1, n=(1024,), lo=(-16.0,), hi=(16.0,), bc=W.FD, beta=400.0, lattice_amp=25.0),
+    W.Problem(dim=2, n=(32, 64), lo=(-6.0, -8.0), hi=(6.0, 8.0), bc=W.FD, beta=50.0,
+              gamma=(1.0, 1.5, 1.0)),
+    W.Problem(dim=2, n=(256, 512), lo=(-16.0, -16.0), hi=(16.0, 16.0), bc=W.FD, beta=500.0,
+              lattice_amp=50.0),
+    W.Problem(dim=3, n=(16, 32, 64), lo=(-5.0, -6.0, -4.0), hi=(5.0, 6.0, 4.0), bc=W.FD, beta=100.0),
+    W.Problem(dim=3, n=(128, 128, 128), lo=(-8.0, -6.0, -4.0), hi=(8.0, 6.0, 4.0), bc=W.FD, beta=200.0,
+              gamma=(1.0, 2.0, 4.0)),
+]
+
+
+def _fcid(p):
+    return f"fd-d{p.dim}-" + "x".join(str(n) for n in p.n)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("p", FD_CASES, ids=_fcid)
+def test_apply_h_fd_matches_oracle(dev, p, prec):
+    phi = _real_field(p, 8)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    t = torch.from_numpy(phi.astype(np.complex128)).to(dt).cuda()
+    out, sc = dev.apply_h(p, t, precision=prec)
+    got = out.cpu().numpy().astype(np.complex128)
+    phi_in = t.cpu().numpy().real.astype(np.float64)
+    ref = disc.h_full(p, phi_in)
+    tol = _bound(p, phi_in, prec)
+    assert float(np.max(np.abs(got.real - ref))) <= tol
+    assert float(np.max(np.abs(got.imag))) == 0.0                # real data stay exactly real
+    up = UnifiedProblem(p)
+    o = up.outputs(up.to_x(phi_in))
+    rtol = 1e-11 if prec == "fp64" else 3e-6
+    assert abs(sc["energy"] - o["energy"]) <= rtol * abs(o["energy"])
+    assert abs(sc["mu"] - o["mu"]) <= rtol * abs(o["mu"])
+    assert abs(sc["norm2"] - up.hvol * float(np.sum(phi_in ** 2))) <= 1e-12
+    assert abs(sc["resid"] - o["resid"]) <= tol + rtol * o["resid"]
+    for a in range(p.dim):
+        assert abs(sc["rms_" + "xyz"[a]] - o["rms"][a]) <= rtol * o["rms"][a] + 1e-14
+
+
+def test_apply_h_fd_complex_data(dev):
+    p = FD_CASES[4]
+    a, b = _real_field(p, 9), _real_field(p, 10)
+    phi = (a + 1j * b) / math.sqrt(2.0)
+    out, _ = dev.apply_h(p, torch.from_numpy(phi).cuda())
+    ref = disc.h_full(p, phi)                       # the FD oracle takes complex data directly
+    assert float(np.max(np.abs(out.cpu().numpy() - ref))) <= _bound(p, phi, "fp64")
+
+
+def test_apply_h_fd_eigenfunction(dev):
+    # beta = 0, V = 0: sin(l pi j / N) sin(m pi k / N) is an eigenvector of the
+    # tridiagonal kinetic matrices with eigenvalue sum of (2/h^2) sin^2(l pi / 2N)
+    p = W.Problem(dim=2, n=(64, 32), lo=(0.0, -1.0), hi=(4.0, 3.0), bc=W.FD, gamma=(0.0, 0.0, 0.0))
+    j = np.arange(1, 64)[None, :]
+    k = np.arange(1, 32)[:, None]
+    l, m = 5, 30
+    f = np.sin(l * np.pi * j / 64) * np.sin(m * np.pi * k / 32) + 0j
+    out, _ = dev.apply_h(p, torch.from_numpy(f).cuda())
+    hx, hy = 4.0 / 64, 4.0 / 32
+    lam = 2 / hx ** 2 * math.sin(l * math.pi / 128) ** 2 + 2 / hy ** 2 * math.sin(m * math.pi / 64) ** 2
+    assert float(np.max(np.abs(out.cpu().numpy() - lam * f))) < 1e-12 * lam
+
+
+def test_hess_vec_fd_matches_oracle(dev):
+    p = FD_CASES[2]
+    up = UnifiedProblem(p)
+    # complex X_k and S (the oracle's FD operator is linear over complex data)
+    xk = math.sqrt(up.hvol) * (_real_field(p, 11) + 0.2j * _real_field(p, 12))
+    s = 1e-2 * math.sqrt(up.hvol) * (_real_field(p, 13) + 0.1j * _real_field(p, 14))
+    delta = 0.37
+    ref = 2.0 * disc.h_lin(p, s) + 4.0 * up.alpha * (np.abs(xk) ** 2 * s + 2.0 * np.real(np.conj(xk) * s) * xk) \
+        + delta * s
+    got = dev.hess_vec(p, torch.from_numpy(xk).cuda(), torch.from_numpy(s).cuda(), delta).cpu().numpy()
+    scale = 2 * _bound(p, s / math.sqrt(up.hvol), "fp64") * math.sqrt(up.hvol) \
+        + 1e-13 * float(np.max(np.abs(ref)))
+    assert float(np.max(np.abs(got - ref))) <= scale
