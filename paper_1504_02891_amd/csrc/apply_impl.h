@@ -21,11 +21,11 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
   TwiddleFetch<N, T> twf;
   twf.fetch(tw1024);
   // loads: the input first; the accumulator, X_k (Hessian-vector) and the
-  // potential of the epilogue roles with it (float64: 0) or after the
-  // inverse transform (float32: 2).  Late loads keep the float32 final pass
-  // at three waves per SIMD (measured 128 vs 164 us at 256^3); the float64
-  // pass is slightly faster with every load issued up front.
-  constexpr int LOADS_AT = EPI && sizeof(T) == 4 ? 2 : 0;
+  // potential of the epilogue roles after the inverse transform, which keeps
+  // them out of the registers live through the transforms (256^3, last pass:
+  // float32 four waves per SIMD, float64 three; measured 103 vs 164 us and
+  // 182 vs 211 us against loading them with the input)
+  constexpr int LOADS_AT = EPI ? 2 : 0;
   cx<T> u[E], tv[E], v[E];
   cx<double> xk[HESS ? E : 1];
   double vp[E];
