@@ -296,7 +296,7 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
   CHK(ws_get(c, WS_APPLY_PROB, sizeof(ProbDev), &pd));
   const int nr = (int)std::min<int64_t>((d.m + 255) / 256, fp64 ? 1024 : 2048);   // residual blocks
   CHK(ws_get(c, WS_APPLY_RPART, (size_t)nr * SR_COUNT * sizeof(double), &rpart));
-  CHK(ws_get(c, WS_APPLY_OUT, (16 + SA_COUNT) * sizeof(double), &out));   // scalars, then slot totals
+  CHK(ws_get(c, WS_APPLY_OUT, (16 + SA_COUNT * 16) * sizeof(double), &out));   // scalars, then chunk totals
   d.t = t;
   d.partF = (double*)part;
   d.part1 = (double*)part;

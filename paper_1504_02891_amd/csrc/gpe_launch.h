@@ -17,8 +17,8 @@ void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64);
 void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
                       int prec64);
-// the last pass's nsum partials per slot into tot[SA_COUNT], then
-// per-block residual maxima (rpart) with mu from those totals
+// the last pass's nsum partials per slot into tot[SA_COUNT * 16] (16 chunk
+// totals per slot), then per-block residual maxima (rpart) with mu from them
 void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, int nsum, const void* phi,
                         const void* hphi, double* rpart, double* tot, int fp64);
 // out[0..9]: the scalars of gpe_apply_h from tot and the residual maxima

@@ -79,26 +79,45 @@ __device__ __forceinline__ void block_sum_partials(const double* part, int count
   block_reduce<NS, NM>(acc, red);
 }
 
-// Totals of the last pass's `count` partials per slot (one per wavefront):
-// workgroup s sums slot s into tot[s].
-__global__ void __launch_bounds__(kSumThreads) k_apply_sums(const ProbDev* probs, int count,
-                                                            double* __restrict__ tot) {
+// Totals of the last pass's `count` partials per slot (one per wavefront),
+// in two fixed-order stages: workgroup (s, c) sums chunk c of slot s into
+// tot[s * kSumChunks + c]; slot_total adds the chunks in order.
+constexpr int kSumChunks = 16;
+__global__ void __launch_bounds__(256) k_apply_sums(const ProbDev* probs, int count, double* __restrict__ tot) {
   __shared__ double red[16];
   const ProbDev& P = probs[0];
-  const int slot = blockIdx.x;
+  const int slot = blockIdx.x / kSumChunks, chunk = blockIdx.x % kSumChunks;
+  const int len = (count + kSumChunks - 1) / kSumChunks;
+  const int lo = chunk * len, hi = min(count, lo + len);
   const double* part = P.partF + (int64_t)slot * count;
-  double acc[1];
-  block_sum_partials<1, 0>(part, count, acc, red);
-  if (threadIdx.x == 0) tot[slot] = acc[0];
+  double acc[1] = {0.0};
+  for (int b0 = lo; b0 < hi; b0 += 8 * 256) {   // thread j: i = lo + j, lo + j + 256, ...
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = b0 + (int)threadIdx.x + j * 256;
+      v[j] = i < hi ? gld<double>(part, i) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[0] += v[j];
+  }
+  block_reduce<1, 0>(acc, red);
+  if (threadIdx.x == 0) tot[blockIdx.x] = acc[0];
+}
+__device__ __forceinline__ double slot_total(const double* tot, int slot) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < kSumChunks; ++c) s += tot[slot * kSumChunks + c];
+  return s;
 }
 
 // E and mu from the last pass's totals: mu = h_vol sum Re(conj(phi) H phi),
 // E = mu - beta/2 h_vol sum |phi|^4 (§1: mu = E + beta/2 int |phi|^4)
 __device__ __forceinline__ double apply_mu(const ProbDev& P, const double* tot) {
-  return P.hvol * tot[SA_MU];
+  return P.hvol * slot_total(tot, SA_MU);
 }
 __device__ __forceinline__ double apply_energy(const ProbDev& P, const double* tot) {
-  return apply_mu(P, tot) - 0.5 * P.beta * P.hvol * tot[SA_QUART];
+  return apply_mu(P, tot) - 0.5 * P.beta * P.hvol * slot_total(tot, SA_QUART);
 }
 
 // q = a / d and a - q d for a < 2^31, d >= 1, rd = 1/d rounded: the FP64
@@ -168,7 +187,7 @@ __global__ void __launch_bounds__(kSumThreads) k_apply_finalize(const ProbDev* p
   double acc[SR_COUNT];
   block_sum_partials<SR_COUNT_SUM, 2>(rpart, nr, acc, red);
   if (threadIdx.x == 0) {
-    const double e = apply_energy(P, tot), epot = P.hvol * tot[SA_POT];
+    const double e = apply_energy(P, tot), epot = P.hvol * slot_total(tot, SA_POT);
     out[0] = e;
     out[1] = apply_mu(P, tot);
     out[2] = sqrt(acc[SR_RES]);
@@ -177,7 +196,7 @@ __global__ void __launch_bounds__(kSumThreads) k_apply_finalize(const ProbDev* p
     out[5] = sqrt(P.hvol * acc[SR_Y2]);
     out[6] = sqrt(P.hvol * acc[SR_Z2]);
     out[7] = acc[SR_MAXD];
-    out[8] = e - epot - 0.5 * P.beta * P.hvol * tot[SA_QUART];
+    out[8] = e - epot - 0.5 * P.beta * P.hvol * slot_total(tot, SA_QUART);
     out[9] = epot;
   }
 }
@@ -293,7 +312,7 @@ void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st
 }
 void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, int nsum, const void* phi,
                         const void* hphi, double* rpart, double* tot, int fp64) {
-  hipLaunchKernelGGL(k_apply_sums, dim3(SA_COUNT), dim3(kSumThreads), 0, s, probs, nsum, tot);
+  hipLaunchKernelGGL(k_apply_sums, dim3(SA_COUNT * kSumChunks), dim3(256), 0, s, probs, nsum, tot);
   if (fp64) hipLaunchKernelGGL(k_apply_resid<double>, dim3(nblk), dim3(256), 0, s, probs,
                                (const cx<double>*)phi, (const cx<double>*)hphi, (const double*)tot, rpart);
   else hipLaunchKernelGGL(k_apply_resid<float>, dim3(nblk), dim3(256), 0, s, probs,
