@@ -118,6 +118,26 @@ def test_batched_mixed_sizes(dev):
     assert np.array_equal(alone, outs[1].cpu().numpy())
 
 
+def test_batched_mixed_discretizations(dev):
+    # Fourier, sine and finite-difference problems of different sizes in one
+    # batch (Omega = 0, real data: real arithmetic for the whole batch); each
+    # follows the trajectory it has when solved alone
+    mk = lambda n, bc, b: W.Problem(dim=2, n=(n, n), lo=(-8.0, -8.0), hi=(8.0, 8.0), bc=bc, beta=b,
+                                    lattice_amp=10.0)
+    probs = [mk(32, W.FOURIER, 100.0), mk(64, W.SINE, 300.0), mk(64, W.FD, 200.0), mk(32, W.FD, 50.0)]
+    phis = [W.gaussian_times_noise(p, 0.02, 20 + i) + 0j for i, p in enumerate(probs)]
+    outs, res = dev.solve_batched(probs, [torch.from_numpy(f).cuda() for f in phis], tol=1e-8,
+                                  precision="mixed")
+    for i, (p, f, o, r) in enumerate(zip(probs, phis, outs, res)):
+        assert r["status"] == 0, (i, r)
+        up = UnifiedProblem(p)
+        ref = regularized_newton(up, up.to_x(f.real), Options(tol=1e-8))
+        _compare(p, o.cpu().numpy().real, ref.x, 1e-8, 1e-9, 1e-5)
+        alone, r0 = _gpu_solve(dev, p, f, tol=1e-8, precision="mixed")
+        assert r0["nfe"] == r["nfe"], (i, r0["nfe"], r["nfe"])
+        assert np.array_equal(alone, o.cpu().numpy()), i
+
+
 def test_cascadic_two_levels(dev):
     probs = [W.Problem(dim=2, n=(32, 32), lo=(-8.0, -8.0), hi=(8.0, 8.0), beta=200.0, omega=w)
              for w in (0.0, 0.3)]
