@@ -622,7 +622,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (o.use_graph) {
+  auto capture = [&]() -> int {
     HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
     capturing = true;
     for (int k = 0; k < chunk; ++k) enqueue_eval(k);
@@ -630,12 +630,50 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     HIPCHK(hipStreamEndCapture(c->s, &graph));
     if (enq_err != hipSuccess) {
       (void)hipGraphDestroy(graph);
-      free_events();
+      graph = nullptr;
       g_last_error = std::string("graph capture: ") + hipGetErrorString(enq_err);
       return GPE_EDEVICE;
     }
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    return GPE_OK;
+  };
+  if (o.use_graph) {
+    const int r = capture();
+    if (r != GPE_OK) {
+      free_events();
+      return r;
+    }
   }
+  // Batches: once the unfinished problems hold at most three quarters of the
+  // launched last-pass tiles, the block maps keep only their tiles and the
+  // chunk is captured again, so that the tail of a batch (its slowest
+  // problems) runs without the finished problems' workgroups.
+  auto compact = [&](const SolverState* hs) -> int {
+    size_t act = 0;
+    for (int i = 0; i < count; ++i)
+      if (!hs[i].done) act += (size_t)pd[i].tiles[dim - 1];
+    if (act == 0 || act * 4 > bm[dim - 1].size() * 3) return GPE_OK;
+    for (int ax = 0; ax < dim; ++ax) {
+      bm[ax].clear();
+      for (int i = 0; i < count; ++i)
+        if (!hs[i].done)
+          for (int t = 0; t < pd[i].tiles[ax]; ++t) bm[ax].push_back(make_int2(i, t));
+    }
+    // staging past the state read-back region; the stream is idle here
+    size_t so2 = (sizeof(SolverState) * count + 255) / 256 * 256;
+    for (int ax = 0; ax < dim; ++ax) {
+      CHK(upload(c, dbm[ax], bm[ax].data(), bm[ax].size() * sizeof(int2), so2));
+      so2 += (bm[ax].size() * sizeof(int2) + 255) / 256 * 256;
+    }
+    if (exec) {
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+      CHK(capture());
+    }
+    return GPE_OK;
+  };
   double pass_ms = 0.0;
   int64_t pass_n = 0;
   void* pin;
@@ -678,6 +716,11 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
     if (all) break;
     if (evals > cap) { rc = GPE_NOT_CONVERGED; break; }
+    if (count > 1) {
+      int r = compact(hs);
+      if (r == GPE_OK) r = pinned_get(c, sizeof(SolverState) * count, &pin);   // the staging may have grown
+      if (r != GPE_OK) { rc = r; break; }
+    }
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
@@ -686,6 +729,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     g_last_error = std::string("solver loop: ") + hipGetErrorString(hipGetLastError());
     return rc;
   }
+  if (rc < 0) return rc;
   HIPCHK(hipEventRecord(c->t1, c->s));
   std::memcpy(st.data(), pin, sizeof(SolverState) * count);
   for (int i = 0; i < count; ++i) launch_write_phi(c->s, P, S, i, pd[i].m, phis[i], prec64);
