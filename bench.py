@@ -158,6 +158,8 @@ def main():
                     help="time every k-th launch of the final pass with HIP events (coprime with the "
                          "64-evaluation chunk, so the samples cover every position in a chunk: the first "
                          "evaluations after a host check run slower)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip gpe_autotune for the workload's grids (run before the warm-up, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed solves of the same workload on the plain float64 path (0: skip)")
@@ -204,6 +206,14 @@ def main():
         outs, rs = api.solve_batched(probs, phis, **kw)
         return rs
 
+    # launch plans: the autotuner times each distinct grid once (untimed);
+    # the solves below use the plans it leaves in the context
+    plans = {}
+    if not a.no_autotune:
+        for p in probs:
+            key = (p.dim, tuple(p.n), getattr(p, "bc", "fourier"))
+            if key not in plans:
+                plans[key] = api.autotune(p, a.precision)
     for _ in range(a.warmup):
         step(a.profile_every)
     torch.cuda.synchronize()
@@ -254,6 +264,7 @@ def main():
         "energy": [r["energy"] for r in last][:4],
         "resid": [r["resid"] for r in last][:4],
         "roofline": roof,
+        "launch_plans": {"x".join(map(str, k[1])): v for k, v in plans.items()},
     }
     if a.fp64_steps > 0 and a.precision == "mixed":
         o64 = dict(opts, precision="fp64")

@@ -407,16 +407,33 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
   CHK(check_options(opts));
   gpe_options o = *opts;
-  // a tuned plan applies when every problem has its grid and the options
-  // leave the launch choices open
-  if (const TunedPlan* tp = find_plan(c, probs[0], o.precision)) {
-    bool all = true;
-    for (int i = 1; i < count; ++i) all = all && find_plan(c, probs[i], o.precision) == tp;
-    if (all) {
-      if (o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0)
-        for (int a = 0; a < 3; ++a) o.threads[a] = tp->threads[a];
-      if (o.step_at == GPE_STEP_AUTO) o.step_at = tp->step_at;
+  // Tuned plans, where the options leave the launch choices open: a batch
+  // whose problems all share one plan takes it whole; otherwise the
+  // workgroup sizes of the largest problem with a plan (a batch's slowest
+  // problems are usually its largest) when they suit every problem's lines.
+  {
+    const TunedPlan* tp = find_plan(c, probs[0], o.precision);
+    bool all = tp != nullptr;
+    for (int i = 1; i < count && all; ++i) all = find_plan(c, probs[i], o.precision) == tp;
+    if (!all) {
+      tp = nullptr;
+      int64_t best = -1;
+      for (int i = 0; i < count; ++i) {
+        const TunedPlan* t = find_plan(c, probs[i], o.precision);
+        int64_t m = 1;
+        for (int a = 0; a < probs[i].dim; ++a) m *= probs[i].n[a];
+        if (t && m > best) { best = m; tp = t; }
+      }
+      for (int i = 0; i < count && tp; ++i)
+        for (int a = 0; a < probs[i].dim; ++a) {
+          const int tl = (probs[i].bc == GPE_BC_SINE ? 2 * probs[i].n[a] : probs[i].n[a]) / kE;
+          if (tl < 1 || tp->threads[a] < tl || tp->threads[a] % tl != 0) tp = nullptr;
+          if (!tp) break;
+        }
     }
+    if (tp && o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0)
+      for (int a = 0; a < 3; ++a) o.threads[a] = tp->threads[a];
+    if (tp && all && o.step_at == GPE_STEP_AUTO) o.step_at = tp->step_at;
   }
   const int prec64 = o.precision == GPE_PREC_FP64;
   const size_t es = prec64 ? 16 : 8;       // element size of F / W arrays
