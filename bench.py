@@ -52,7 +52,15 @@ def workload(name):
     if name == "batch2d":
         probs, phis = W.rotating_sweep_2d()
         return probs, phis, "64 rotating 2D problems, 64^2/128^2/256^2 on [-12,12]^2"
+    if name == "cascade2d":
+        probs, phis, _ = W.cascade_2d(count=CASCADE[0])
+        return probs, phis, (f"{CASCADE[0]} rotating 2D problems, Omega from 0.80 in steps of 0.01, beta=5000 on "
+                             f"[-20,20]^2, cascadic levels 64^2 -> {64 << (CASCADE[1] - 1)}^2 (Algorithm 3)")
     raise SystemExit(f"unknown workload {name}")
+
+
+CASCADE = [16, 4]           # cascade2d: problems, levels (64^2 .. 512^2); --cascade-problems/--cascade-levels
+CASCADE_LEVEL_TOL = 1e-4    # residual at which a coarse level hands over to the next
 
 
 def cpu_baseline(probs, phi0s, gpu_nfe, budget_s, opts):
@@ -148,9 +156,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rot2d", choices=["rot2d", "harm1d", "lattice3d", "batch2d"])
+    ap.add_argument("--workload", default="rot2d", choices=["rot2d", "harm1d", "lattice3d", "batch2d", "cascade2d"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cascade-problems", type=int, default=16,
+                    help="cascade2d: problems (the full configuration, 16, runs for minutes)")
+    ap.add_argument("--cascade-levels", type=int, default=4, help="cascade2d: levels from 64^2 (4: up to 512^2)")
+    ap.add_argument("--tol", type=float, default=None,
+                    help="residual tolerance (default 1e-6; 1e-7 for cascade2d)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="Newton-step cap per solve (lower it only for short profiler runs)")
@@ -182,14 +194,19 @@ def main():
         print(json.dumps({"hphi": hphi_bandwidth()}), flush=True)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (independent problems shard without "
+                                   "communication); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
     import torch
     from paper_1504_02891_amd import api
 
+    CASCADE[:] = [a.cascade_problems, a.cascade_levels]
     probs, phi0s, desc = workload(a.workload)
+    cascade = a.workload == "cascade2d"
+    if a.tol is None:
+        a.tol = 1e-7 if cascade else 1e-6
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     phis = [torch.from_numpy(np.asarray(f, dtype=np.complex128)).to(dev) for f in phi0s]
@@ -200,6 +217,9 @@ def main():
     # nodes, which add their packets' time to the interval)
     def step(profile):
         kw = dict(opts, profile=profile, use_graph=0 if profile else 1)
+        if cascade:
+            outs, rs = api.solve_cascadic(probs, phis, CASCADE[1], level_tol=CASCADE_LEVEL_TOL, **kw)
+            return rs
         if len(probs) == 1:
             out, r = api.solve(probs[0], phis[0], **kw)
             return [r]
@@ -210,10 +230,12 @@ def main():
     # the solves below use the plans it leaves in the context
     plans = {}
     if not a.no_autotune:
-        for p in probs:
-            key = (p.dim, tuple(p.n), getattr(p, "bc", "fourier"))
-            if key not in plans:
-                plans[key] = api.autotune(p, a.precision)
+        for p0 in probs:
+            for lvl in range(CASCADE[1] if cascade else 1):      # every level's grid
+                p = p0.with_n([n << lvl for n in p0.n]) if lvl else p0
+                key = (p.dim, tuple(p.n), getattr(p, "bc", "fourier"))
+                if key not in plans:
+                    plans[key] = api.autotune(p, a.precision)
     for _ in range(a.warmup):
         step(a.profile_every)
     torch.cuda.synchronize()
@@ -244,11 +266,18 @@ def main():
     avg_ms = ms / max(launches, 1)
     bpl = byt / max(nlaunch, 1)
     achieved = bpl / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(a.workload, a.precision),
+    if cascade:
+        # the result counters add the evaluations of all four grid sizes: no
+        # per-launch byte count (the single-grid workloads carry the roofline)
+        achieved, bpl = None, None
+    roof = {"bound": "hbm", "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(a.workload, a.precision),
             "kernel": "k_solver_pass<R_FINAL>", "avg_launch_us": round(avg_ms * 1e3, 3),
             "timing": f"dispatch-stamped HIP events on every {a.profile_every}th launch of the timed steps",
-            "timed_launches": launches, "launches": nlaunch, "bytes_per_launch": round(bpl)}
+            "timed_launches": launches, "launches": nlaunch,
+            "bytes_per_launch": None if bpl is None else round(bpl)}
 
     out = {
         "metric": "ground-state solves/sec + H\u00b7\u03c6 HBM GB/s; mixed vs FP64 GPU at resid 1e-6",
@@ -266,7 +295,9 @@ def main():
         "roofline": roof,
         "launch_plans": {"x".join(map(str, k[1])): v for k, v in plans.items()},
     }
-    if a.fp64_steps > 0 and a.precision == "mixed":
+    if cascade:
+        out["config"]["grid_points"] = [int(np.prod(p.n[: p.dim])) << (2 * (CASCADE[1] - 1)) for p in probs]
+    if a.fp64_steps > 0 and a.precision == "mixed" and not cascade:
         o64 = dict(opts, precision="fp64")
         if len(probs) == 1:
             api.solve(probs[0], phis[0], **o64)            # warm-up
@@ -286,7 +317,7 @@ def main():
                        "energy": [r["energy"] for r in r64[-1]][:4], "resid": [r["resid"] for r in r64[-1]][:4]}
     if not a.no_hphi:
         out["hphi"] = hphi_bandwidth()
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and not cascade:      # the oracle's sample is one grid's Algorithm 2
         out["cpu_baseline"] = cpu_baseline(probs, phi0s, last[0]["nfe"], a.cpu_budget, opts)
     print(json.dumps(out), flush=True)
 

@@ -259,7 +259,7 @@ int gpe_autotune(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, int32
  * the spectrum is zero-padded and the coarse Nyquist coefficient split half
  * and half between +n and -n.  phi_c, phi_f: DEVICE complex128 arrays.
  * fine must equal coarse with every n doubled.  Fourier problems only
- * (GPE_EUNSUPPORTED for GPE_BC_SINE).
+ * (GPE_EUNSUPPORTED for GPE_BC_SINE and GPE_BC_FD).
  */
 int gpe_prolong(gpe_ctx* ctx, const gpe_problem* coarse, const gpe_problem* fine,
                 const void* phi_c, void* phi_f);
