@@ -81,14 +81,14 @@ extern "C" {
 /* ---- problem ------------------------------------------------------------ */
 typedef struct gpe_problem {
     int32_t dim;          /* 1, 2 or 3 */
-    int32_t bc;           /* GPE_BC_FOURIER or GPE_BC_SINE */
+    int32_t bc;           /* GPE_BC_FOURIER, GPE_BC_SINE or GPE_BC_FD */
     int32_t n[3];         /* per axis (x, y, z), entries beyond dim ignored.  Fourier: n periodic
-                             points x_j = lo + j h, j < n.  Sine: n intervals, n-1 interior
-                             points x_j = lo + j h, 0 < j < n.  h = (hi - lo)/n.  Arrays hold
-                             the points of every axis, x fastest */
+                             points x_j = lo + j h, j < n.  Sine and finite differences: n
+                             intervals, n-1 interior points x_j = lo + j h, 0 < j < n.
+                             h = (hi - lo)/n.  Arrays hold the points of every axis, x fastest */
     double lo[3], hi[3];  /* box U = prod (lo_i, hi_i), lo_i < hi_i */
     double beta;          /* interaction constant */
-    double omega;         /* rotation speed; must be 0 when dim == 1 or bc is GPE_BC_SINE */
+    double omega;         /* rotation speed; must be 0 when dim == 1 or bc is GPE_BC_SINE or GPE_BC_FD */
     double gamma[3];      /* harmonic trap V = 1/2 sum gamma_i^2 x_i^2 (§1) */
     double lattice_amp;   /* optical lattice A * sum sin^2(k x_i) (§4.2, §4.4); 0 = none */
     double lattice_k;     /* k of the lattice (pi/4 in the paper) */
@@ -110,7 +110,9 @@ typedef struct gpe_options {
     double renorm_tol;                    /* renormalise when | ||X||^2 - 1 | > renorm_tol (§4) */
     double eta1, eta2, gamma_shrink, gamma_grow;  /* trust-region ratio test and delta update (§3.2) */
     double delta0, delta_min, delta_max;          /* regularisation delta */
-    int32_t chunk;        /* evaluations per host check of the done flags (graph size) */
+    int32_t chunk;        /* evaluations per host check of the done flags (graph size); in a
+                             batch, finished problems are dropped from the launches at these
+                             checks */
     int32_t use_graph;    /* 1: replay chunks as a captured hipGraph; 0: plain launches */
     int32_t profile;      /* k > 0: time the last-axis pass of every k-th evaluation with a pair of
                              HIP events: stamped by the kernel's own dispatch with plain launches
