@@ -137,6 +137,13 @@ typedef struct gpe_options {
                              remaining steps (the stop test is then taken in FP64); 0 = never:
                              the FP32 residual decides (default 100) */
     int32_t reserved1;
+    double switch_resid;  /* mixed precision, Algorithm 2: once the residual of an outer (FP64)
+                             evaluation is below switch_resid but not yet below tol, the outer
+                             iterate X_k starts an FP64 run of Algorithm 2 (its K_init steps of
+                             Algorithm 1 first, the regularisation delta kept) with the remaining
+                             Newton steps: the Newton
+                             subproblems in FP32 stall near the FP32 residual floor.  0 = never
+                             (default 1e-4, about ten times the floor of the benchmark grids) */
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */
@@ -148,8 +155,9 @@ typedef struct gpe_result {
     int32_t nfe_fp64;     /* of which evaluated in float64 */
     int32_t backtracks;   /* step-size reductions */
     int32_t rejections;   /* rejected Newton trial points */
-    int32_t switch_iter;  /* mixed precision, Algorithm 1: steps taken in FP32 before the
-                             FP64 continuation (0 = no switch) */
+    int32_t switch_iter;  /* mixed precision: Algorithm 1 steps (alone, or the K_init and inner
+                             steps of Algorithm 2) taken in FP32 before the FP64 continuation
+                             (at least 1 when it took place; 0 = no switch) */
     double energy;        /* E_h(phi)  (§2) */
     double mu;            /* E + beta/2 int |phi|^4  (§1) */
     double resid;         /* ||H(phi)phi - mu phi||_inf */

@@ -56,7 +56,8 @@ class Options(C.Structure):
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("profile", C.c_int32),
                 ("real_field", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32),
                 ("stop_rule", C.c_int32), ("monotone", C.c_int32), ("eps0", C.c_double),
-                ("crit2_tol", C.c_double), ("switch_window", C.c_int32), ("reserved1", C.c_int32)]
+                ("crit2_tol", C.c_double), ("switch_window", C.c_int32), ("reserved1", C.c_int32),
+                ("switch_resid", C.c_double)]
 
 
 class Result(C.Structure):

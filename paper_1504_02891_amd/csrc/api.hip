@@ -265,6 +265,7 @@ void set_default(gpe_options* o) {
   o->crit2_tol = 1e-8;
   o->switch_window = 100;
   o->reserved1 = 0;
+  o->switch_resid = 1e-4;
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +361,7 @@ void init_state(SolverState& S, const gpe_options& o) {
   S.eta = o.monotone ? 0.0 : o.eta;      // monotone Armijo: C = F(X_k)
   S.stop_rule = o.stop_rule; S.eps0 = o.eps0; S.crit2_tol = o.crit2_tol;
   S.switch_window = o.switch_window; S.since_best = 0; S.best_r = INFINITY;
+  S.switch_r = o.switch_resid;
   S.renorm_tol = o.renorm_tol;
   S.eta1 = o.eta1; S.eta2 = o.eta2; S.gshrink = o.gamma_shrink; S.ggrow = o.gamma_grow;
   S.delta_min = o.delta_min; S.delta_max = o.delta_max;
@@ -380,7 +382,8 @@ int check_options(const gpe_options* o) {
   if (o->real_field < -1 || o->real_field > 1) return GPE_EINVAL;
   if (o->stop_rule < GPE_STOP_RESID || o->stop_rule > GPE_STOP_CRIT2) return GPE_EINVAL;
   if (o->monotone != 0 && o->monotone != 1) return GPE_EINVAL;
-  if (!(o->eps0 >= 0.0) || !(o->crit2_tol >= 0.0) || o->switch_window < 0) return GPE_EINVAL;
+  if (!(o->eps0 >= 0.0) || !(o->crit2_tol >= 0.0) || o->switch_window < 0 ||
+      !(o->switch_resid >= 0.0)) return GPE_EINVAL;
   return GPE_OK;
 }
 
@@ -402,8 +405,10 @@ const TunedPlan* find_plan(const gpe_ctx* c, const gpe_problem& p, int prec) {
   return nullptr;
 }
 
+// delta0 (optional): per-problem initial regularisation delta (an FP64
+// continuation keeps the delta its mixed-precision run reached)
 int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
-               gpe_result* results) {
+               gpe_result* results, const double* delta0 = nullptr) {
   if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
   CHK(check_options(opts));
   gpe_options o = *opts;
@@ -565,7 +570,10 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       for (int t = 0; t < pd[i].tiles[ax]; ++t) bm[ax].push_back(make_int2(i, t));
   for (int ax = 0; ax < dim; ++ax) CHK(ws_get(c, WS_BMAP0 + ax, bm[ax].size() * sizeof(int2), &dbm[ax]));
   std::vector<SolverState> st(count);
-  for (int i = 0; i < count; ++i) init_state(st[i], o);
+  for (int i = 0; i < count; ++i) {
+    init_state(st[i], o);
+    if (delta0) st[i].delta = std::min(std::max(delta0[i], o.delta_min), o.delta_max);
+  }
   // uploads (staging offsets keep the pieces apart)
   size_t so = 0;
   CHK(upload(c, dvax, vaxis.data(), vaxis.size() * sizeof(double), so));
@@ -797,10 +805,12 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   return worst;
 }
 
-// Solve, then continue in FP64 the problems whose mixed-precision Algorithm 1
-// stalled at the FP32 floor (internal status kStatusStalled): the iterate
-// each left in its phi buffer starts an FP64 run of Algorithm 1 with the
-// remaining step budget.  Counters add up; the outputs are the FP64 run's.
+// Solve, then continue in FP64 the problems whose mixed-precision run handed
+// over (internal status kStatusStalled: Algorithm 1 at the FP32 floor, or
+// Algorithm 2 at the handover residual): the iterate each left in its phi
+// buffer starts an FP64 run of the same algorithm with the remaining step
+// (Algorithm 1) or Newton-step (Algorithm 2) budget.  Counters add up; the
+// outputs are the FP64 run's.
 int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
                  gpe_result* results) {
   int rc = solve_impl(c, count, probs, opts, phis, results);
@@ -811,22 +821,27 @@ int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_opti
   if (idx.empty()) return rc;
   std::vector<gpe_problem> sp;
   std::vector<void*> sphi;
-  int used = 0;
+  std::vector<double> d0;
+  int used = 0, used_outer = 0;
   for (int i : idx) {
     sp.push_back(probs[i]);
     sphi.push_back(phis[i]);
+    d0.push_back(results[i].delta);
     used = std::max(used, results[i].inner_iters);
+    used_outer = std::max(used_outer, results[i].outer_iters);
   }
   gpe_options o2 = *opts;
   o2.precision = GPE_PREC_FP64;
-  o2.max_iter = std::max(0, opts->max_iter - used);
+  if (opts->algorithm == GPE_ALG1) o2.max_iter = std::max(0, opts->max_iter - used);
+  else o2.max_outer = std::max(0, opts->max_outer - used_outer);
   std::vector<gpe_result> r2(idx.size());
-  const int rc2 = solve_impl(c, (int)idx.size(), sp.data(), &o2, sphi.data(), r2.data());
+  const int rc2 = solve_impl(c, (int)idx.size(), sp.data(), &o2, sphi.data(), r2.data(),
+                             opts->algorithm == GPE_ALG1 ? nullptr : d0.data());
   if (rc2 < 0) return rc2;
   for (size_t k = 0; k < idx.size(); ++k) {
     gpe_result& a = results[idx[k]];
     gpe_result b = r2[k];
-    b.switch_iter = a.inner_iters;
+    b.switch_iter = std::max(1, a.inner_iters);
     b.outer_iters += a.outer_iters;
     b.inner_iters += a.inner_iters;
     b.nfe += a.nfe;
@@ -1025,6 +1040,7 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
   o.tol = 0.0;
   o.chunk = 32;
   o.switch_window = 0;
+  o.switch_resid = 0.0;
   double best = INFINITY;
   TunedPlan bp{};
   for (int t0 : cand[0])

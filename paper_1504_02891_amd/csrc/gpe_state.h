@@ -121,7 +121,8 @@ struct SolverState {
   double tol, tau0, rho1, eta, sigma, renorm_tol;
   double eta1, eta2, gshrink, ggrow, delta_min, delta_max;
   double eps0, crit2_tol;                  // thresholds of the step-length stop rules
-  double best_r, pad_d;                    // best residual of Algorithm 1 (stall test)
+  double best_r;                           // best residual of Algorithm 1 (stall test)
+  double switch_r;                         // mixed Algorithm 2: FP64 handover residual
   int32_t k_init, k_sub, m_max, max_iter;
   int32_t pad4, pad5;                      // whole 16-byte words (read with 16-byte loads)
 };

@@ -134,6 +134,9 @@ __device__ __forceinline__ void step_logic(const ProbDev& P, SolverState& S, con
       if (S.k == 0) {
         S.r_outer = rb;
         if (S.stop_rule != STOP_CRIT2 && rb < S.tol) { finish(S, 0, SRC_XK); return; }
+        // mixed precision: X_k (FP64) continues in an FP64 run once its
+        // residual reaches the handover level
+        if (!prec64 && rb < S.switch_r) { finish(S, kStatusStalled, SRC_XK); return; }
         if (S.outer >= S.max_outer) { finish(S, 1, SRC_XK); return; }
         const double npk = sqrt(S.np2_b);
         S.forcing = fmin(0.1, npk) * npk;

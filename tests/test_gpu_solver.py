@@ -420,6 +420,28 @@ def test_mixed_alg1_switches_to_fp64(dev):
     assert r0["status"] == 1 and r0["switch_iter"] == 0
 
 
+@pytest.mark.parametrize("case", ["lattice-3d", "rotating-2d"])
+def test_mixed_alg2_hands_over_to_fp64(dev, case):
+    # mixed Algorithm 2 hands X_k to an FP64 run of Algorithm 2 once an outer
+    # residual is below switch_resid; with switch_resid = 0 it stays mixed
+    if case == "lattice-3d":
+        p = W.Problem(dim=3, n=(32, 32, 32), lo=(-8.0,) * 3, hi=(8.0,) * 3, beta=200.0, lattice_amp=25.0)
+        phi0, tol, sw = W.gaussian_times_noise(p, 0.01, 3), 1e-7, 1e-4
+    else:
+        p = W.Problem(dim=2, n=(64, 64), lo=(-10.0, -10.0), hi=(10.0, 10.0), beta=500.0, omega=0.25)
+        phi0, tol, sw = W.rotating_initial(p, 0.25, 2), 1e-8, 1e-5
+    up = UnifiedProblem(p)
+    ref = regularized_newton(up, up.to_x(phi0), Options(tol=tol, max_outer=3000))
+    assert ref.converged
+    phi, res = _gpu_solve(dev, p, phi0, tol=tol, precision="mixed", switch_resid=sw, max_outer=3000)
+    assert res["status"] == 0 and res["resid"] < tol, res
+    assert 0 < res["switch_iter"] <= res["inner_iters"], res
+    assert res["nfe_fp64"] > res["nfe_outer"], res        # FP64 Algorithm 1 steps after the handover
+    _compare(p, phi, ref.x, tol, 1e-9, 1e-5)
+    phi0_, r0 = _gpu_solve(dev, p, phi0, tol=tol, precision="mixed", switch_resid=0.0, max_outer=3000)
+    assert r0["status"] == 0 and r0["switch_iter"] == 0, r0
+    _compare(p, phi0_, ref.x, tol, 1e-9, 1e-5)
+
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_rotating_3d_small(dev, prec):
@@ -448,8 +470,10 @@ def test_autotune_plan(dev):
         t = plan["threads"][a]
         assert t in (64, 128, 256) and t % (n // 8) == 0, plan
     phi0 = W.rotating_initial(p, 0.3, 12)
-    phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed")
+    # no FP64 continuation: its passes would take the FP64 plan of the grid
+    # in one run and the given threads in the other
+    phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed", switch_resid=0.0)
     phi_b, rb = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed", threads=plan["threads"][:2] + [0],
-                           step_at=plan["step_at"])
+                           step_at=plan["step_at"], switch_resid=0.0)
     assert ra["status"] == 0 and ra["nfe"] == rb["nfe"]
     assert np.array_equal(phi_a, phi_b)
