@@ -97,21 +97,30 @@ def cpu_baseline(probs, phi0s, gpu_nfe, budget_s, opts):
                        f"by the {gpu_nfe} evaluations of the GPU solve")}
 
 
-def recorded_traffic(workload_name, precision):
+def recorded_traffic(workload_name, ev32, ev64):
     """HBM bytes per final-pass launch from the committed rocprofv3 counter
-    record, or None when that record is for other sources or another workload."""
+    records of the pass's FP32 and FP64 instances, weighted by the evaluations
+    each ran; None when a record needed is missing, for other sources or for
+    another workload."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"final_pass_{workload_name}_256_{precision}_traffic.json")
-    if workload_name != "rot2d" or not os.path.exists(path):
+    if workload_name != "rot2d" or ev32 + ev64 == 0:
         return None
-    rec = json.load(open(path))
-    h = hashlib.sha256()
-    for src in rec["kernel_sources"]:
-        with open(os.path.join(ROOT, "paper_1504_02891_amd", "csrc", src), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec["kernel_sha256"]:
-        return None
-    return round(rec["traffic_bytes_per_launch"])
+    tot = 0.0
+    for prec, ev in (("mixed", ev32), ("fp64", ev64)):
+        if ev == 0:
+            continue
+        path = os.path.join(ROOT, "profiles", f"final_pass_{workload_name}_256_{prec}_traffic.json")
+        if not os.path.exists(path):
+            return None
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for src in rec["kernel_sources"]:
+            with open(os.path.join(ROOT, "paper_1504_02891_amd", "csrc", src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != rec["kernel_sha256"]:
+            return None
+        tot += ev * rec["traffic_bytes_per_launch"]
+    return round(tot / (ev32 + ev64))
 
 
 def hphi_bandwidth(n=256, reps=20):
@@ -173,6 +182,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip gpe_autotune for the workload's grids (run before the warm-up, untimed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--switch-resid", type=float, default=None,
+                    help="mixed Algorithm 2: residual of the FP64 handover (library default 1e-4; 0: the "
+                         "whole solve stays mixed)")
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed solves of the same workload on the plain float64 path (0: skip)")
     ap.add_argument("--no-hphi", action="store_true", help="skip the 256^3 H(phi)phi bandwidth measurement")
@@ -211,6 +223,8 @@ def main():
     torch.cuda.set_device(dev)
     phis = [torch.from_numpy(np.asarray(f, dtype=np.complex128)).to(dev) for f in phi0s]
     opts = dict(tol=a.tol, precision=a.precision, max_outer=a.max_outer)
+    if a.switch_resid is not None:
+        opts["switch_resid"] = a.switch_resid
 
     # timed steps: plain launches with every k-th last-axis pass timed by
     # events stamped by its own dispatch (graph replay would need event
@@ -228,14 +242,17 @@ def main():
 
     # launch plans: the autotuner times each distinct grid once (untimed);
     # the solves below use the plans it leaves in the context
+    # (a mixed solve's FP64 continuation and the fp64 comparison solve take
+    # the FP64 plans)
     plans = {}
     if not a.no_autotune:
         for p0 in probs:
             for lvl in range(CASCADE[1] if cascade else 1):      # every level's grid
                 p = p0.with_n([n << lvl for n in p0.n]) if lvl else p0
-                key = (p.dim, tuple(p.n), getattr(p, "bc", "fourier"))
-                if key not in plans:
-                    plans[key] = api.autotune(p, a.precision)
+                for prec in (("mixed", "fp64") if a.precision == "mixed" else ("fp64",)):
+                    key = (prec, tuple(p.n), getattr(p, "bc", "fourier"))
+                    if key not in plans:
+                        plans[key] = api.autotune(p, prec)
     for _ in range(a.warmup):
         step(a.profile_every)
     torch.cuda.synchronize()
@@ -253,13 +270,21 @@ def main():
     # roofline of the final pass over every timed step: algorithmic bytes per
     # launch (all problems' evaluations in that launch, by mode) divided by the
     # event-timed average launch duration (every k-th launch sampled)
-    mb = FINAL_BYTES[a.precision]
+    # (a mixed solve's evaluations after the FP64 handover run the FP64
+    # instance of the pass: each is priced by the byte model of its precision)
+    mb, m64 = FINAL_BYTES["mixed"], FINAL_BYTES["fp64"]
     pts = [int(np.prod(p.n[: p.dim])) for p in probs]
     byt, nlaunch = 0.0, 0
     launches, ms = 0, 0.0
+    ev32 = ev64 = 0
     for rs in results:
         for r, m in zip(rs, pts):
-            byt += m * (r["nfe_f"] * mb["f"] + r["nfe_w"] * mb["w"] + r["nfe_outer"] * mb["o"])
+            for k, key in enumerate(("nfe_f", "nfe_w", "nfe_outer")):
+                mode = key[4]
+                n32 = r["nfe_mixed"][k]
+                byt += m * (n32 * mb[mode] + (r[key] - n32) * m64[mode])
+                ev32 += n32
+                ev64 += r[key] - n32
         nlaunch += max(r["nfe"] for r in rs)
         launches += rs[0]["pass_launches"]
         ms += rs[0]["pass_ms"]
@@ -273,8 +298,9 @@ def main():
     roof = {"bound": "hbm", "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": recorded_traffic(a.workload, a.precision),
-            "kernel": "k_solver_pass<R_FINAL>", "avg_launch_us": round(avg_ms * 1e3, 3),
+            "traffic": recorded_traffic(a.workload, ev32, ev64),
+            "kernel": "k_solver_pass<R_FINAL>", "evaluations": {"fp32_instance": ev32, "fp64_instance": ev64},
+            "avg_launch_us": round(avg_ms * 1e3, 3),
             "timing": f"dispatch-stamped HIP events on every {a.profile_every}th launch of the timed steps",
             "timed_launches": launches, "launches": nlaunch,
             "bytes_per_launch": None if bpl is None else round(bpl)}
@@ -293,7 +319,7 @@ def main():
         "energy": [r["energy"] for r in last][:4],
         "resid": [r["resid"] for r in last][:4],
         "roofline": roof,
-        "launch_plans": {"x".join(map(str, k[1])): v for k, v in plans.items()},
+        "launch_plans": {k[0] + " " + "x".join(map(str, k[1])): v for k, v in plans.items()},
     }
     if cascade:
         out["config"]["grid_points"] = [int(np.prod(p.n[: p.dim])) << (2 * (CASCADE[1] - 1)) for p in probs]

@@ -172,6 +172,9 @@ typedef struct gpe_result {
     int32_t nfe_outer;    /* float64 evaluations of F at outer iterates */
     int32_t pass_launches;/* profile: timed (sampled) launches of the last-axis pass */
     double pass_ms;       /* profile: summed event time of those launches */
+    int32_t nfe_mixed[3]; /* of nfe_f, nfe_w, nfe_outer: the evaluations run by the mixed-precision
+                             passes (the rest ran in an FP64 continuation or an FP64 solve) */
+    int32_t reserved2;
 } gpe_result;
 
 typedef struct gpe_ctx gpe_ctx;

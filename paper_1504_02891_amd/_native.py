@@ -68,11 +68,13 @@ class Result(C.Structure):
                 ("norm_err", C.c_double), ("rms", C.c_double * 3), ("max_dens", C.c_double),
                 ("delta", C.c_double), ("time_ms", C.c_double),
                 ("nfe_f", C.c_int32), ("nfe_w", C.c_int32), ("nfe_outer", C.c_int32),
-                ("pass_launches", C.c_int32), ("pass_ms", C.c_double)]
+                ("pass_launches", C.c_int32), ("pass_ms", C.c_double),
+                ("nfe_mixed", C.c_int32 * 3), ("reserved2", C.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "rms"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("rms", "nfe_mixed")}
         d["rms"] = list(self.rms)
+        d["nfe_mixed"] = list(self.nfe_mixed)
         return d
 
 

@@ -781,6 +781,11 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     r.nfe_outer = s.nfe_o;
     r.pass_launches = (int32_t)pass_n;
     r.pass_ms = pass_ms;
+    if (!prec64) {
+      r.nfe_mixed[0] = s.nfe_f;
+      r.nfe_mixed[1] = s.nfe_w;
+      r.nfe_mixed[2] = s.nfe_o;
+    }
     if (r.status >= 0) {
       // outputs recomputed in float64 from the returned phi
       double sc[10];
@@ -854,6 +859,7 @@ int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_opti
     b.time_ms += a.time_ms;
     b.pass_launches += a.pass_launches;
     b.pass_ms += a.pass_ms;
+    for (int k = 0; k < 3; ++k) b.nfe_mixed[k] += a.nfe_mixed[k];
     a = b;
   }
   int worst = GPE_OK;
@@ -1135,7 +1141,7 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
   }
   CHK(end_call(c));
   std::vector<gpe_result> tmp(count);
-  std::vector<int64_t> nfe(count, 0), nfe64(count, 0), outer(count, 0), inner(count, 0);
+  std::vector<int64_t> nfe(count, 0), nfe64(count, 0), outer(count, 0), inner(count, 0), nmix(3 * count, 0);
   double tms = 0.0;
   int rc = GPE_OK;
   for (int l = 0; l < nlevels; ++l) {
@@ -1156,6 +1162,7 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
     for (int i = 0; i < count; ++i) {
       nfe[i] += tmp[i].nfe; nfe64[i] += tmp[i].nfe_fp64;
       outer[i] += tmp[i].outer_iters; inner[i] += tmp[i].inner_iters;
+      for (int k = 0; k < 3; ++k) nmix[3 * i + k] += tmp[i].nfe_mixed[k];
     }
     tms += tmp[0].time_ms;
     if (l < nlevels - 1) {
@@ -1174,6 +1181,7 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
     results[i].nfe_fp64 = (int32_t)nfe64[i];
     results[i].outer_iters = (int32_t)outer[i];
     results[i].inner_iters = (int32_t)inner[i];
+    for (int k = 0; k < 3; ++k) results[i].nfe_mixed[k] = (int32_t)nmix[3 * i + k];
     results[i].time_ms = tms;
   }
   return rc;
