@@ -437,10 +437,19 @@ def test_mixed_alg2_hands_over_to_fp64(dev, case):
     assert res["status"] == 0 and res["resid"] < tol, res
     assert 0 < res["switch_iter"] <= res["inner_iters"], res
     assert res["nfe_fp64"] > res["nfe_outer"], res        # FP64 Algorithm 1 steps after the handover
+    # evaluation accounting: every evaluation has one mode; the mixed passes ran
+    # part of them, the FP64 continuation the rest
+    assert res["nfe_f"] + res["nfe_w"] + res["nfe_outer"] == res["nfe"], res
+    assert all(0 <= a <= b for a, b in zip(res["nfe_mixed"], (res["nfe_f"], res["nfe_w"], res["nfe_outer"]))), res
+    assert res["nfe_mixed"][0] > 0 and res["nfe_mixed"][2] > 0, res   # K_init steps; the handover's outer evaluation
+    assert sum(res["nfe_mixed"]) < res["nfe"], res
     _compare(p, phi, ref.x, tol, 1e-9, 1e-5)
     phi0_, r0 = _gpu_solve(dev, p, phi0, tol=tol, precision="mixed", switch_resid=0.0, max_outer=3000)
     assert r0["status"] == 0 and r0["switch_iter"] == 0, r0
+    assert r0["nfe_mixed"] == [r0["nfe_f"], r0["nfe_w"], r0["nfe_outer"]], r0
     _compare(p, phi0_, ref.x, tol, 1e-9, 1e-5)
+    _, r64 = _gpu_solve(dev, p, phi0, tol=tol, precision="fp64", max_outer=3000)
+    assert r64["nfe_mixed"] == [0, 0, 0] and r64["switch_iter"] == 0, r64
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
