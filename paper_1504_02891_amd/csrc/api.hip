@@ -33,6 +33,7 @@ thread_local std::string g_last_error;
 
 constexpr int kSolverThreads = 128;   // threads per workgroup of every solver pass
 constexpr int kApplyThreads = 128;
+constexpr int64_t kRereadTiles = 1024;  // final-pass tiles from which its epilogue re-reads (256 CUs x 4)
 
 // Workspace slots owned by a context (grown on demand, freed at destroy).
 enum WsSlot {
@@ -624,6 +625,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   bool capturing = false;
   auto enqueue_eval = [&](int k) {
+    // final pass: the epilogue re-reads its inputs once the launch has enough
+    // tiles to be bandwidth bound (four workgroups per compute unit)
+    const int reread = (int64_t)bm[dim - 1].size() >= kRereadTiles ? 1 : 0;
     const bool prof = sampled(eval_index++);
     const bool nodes = prof && capturing;                    // event record nodes around the pass
     hipEvent_t e0 = prof && !capturing ? pev[2 * k] : nullptr, e1 = prof && !capturing ? pev[2 * k + 1] : nullptr;
@@ -637,7 +641,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
     if (nodes) record(pev[2 * k]);
     launch_solver_pass(c->s, last, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
-                       bmap(dim - 1), c->twd, c->twf, e0, e1);
+                       bmap(dim - 1), c->twd, c->twf, e0, e1, reread);
     if (nodes) record(pev[2 * k + 1]);
     if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S, prec64);
   };

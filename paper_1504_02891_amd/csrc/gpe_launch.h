@@ -7,10 +7,11 @@
 
 namespace gpe {
 // bmap: null for a single problem; ev0/ev1 (optional, plain launches only):
-// events stamped by the dispatch itself at the kernel's start and end
+// events stamped by the dispatch itself at the kernel's start and end;
+// reread (final and solo roles): the epilogue re-reads the trial inputs
 void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int threads, size_t smem,
                         const ProbDev* probs, SolverState* st, const int2* bmap, const void* twd, const void* twf,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int reread = 0);
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
 void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64);

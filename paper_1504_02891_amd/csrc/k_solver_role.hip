@@ -14,17 +14,24 @@
 #define GPE_CAT(a, b, c) GPE_CAT2(a, b, c)
 
 namespace gpe {
+template <bool RR>
+static void launch(hipStream_t s, int nblocks, int threads, size_t smem, const ProbDev* probs, SolverState* st,
+                   const int2* bmap, const void* twd, const void* twf, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0) {
+    // events stamped by the dispatch itself (start and end of this kernel)
+    hipExtLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0), RR>), dim3(nblocks), dim3(threads), smem, s,
+                          ev0, ev1, 0, probs, st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+  } else {
+    hipLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0), RR>), dim3(nblocks), dim3(threads), smem, s,
+                       probs, st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+  }
+}
 void GPE_CAT(launch_solver_pass_r, GPE_ROLE, GPE_PREC64)(hipStream_t s, int nblocks, int threads, size_t smem,
                                                          const ProbDev* probs, SolverState* st,
                                                          const int2* bmap, const void* twd, const void* twf,
-                                                         hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0) {
-    // events stamped by the dispatch itself (start and end of this kernel)
-    hipExtLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0)>), dim3(nblocks), dim3(threads), smem, s, ev0,
-                          ev1, 0, probs, st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
-  } else {
-    hipLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0)>), dim3(nblocks), dim3(threads), smem, s, probs,
-                       st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
-  }
+                                                         hipEvent_t ev0, hipEvent_t ev1, int reread) {
+  constexpr bool epi = GPE_ROLE == R_FINAL || GPE_ROLE == R_SOLO;
+  if (epi && reread) launch<epi>(s, nblocks, threads, smem, probs, st, bmap, twd, twf, ev0, ev1);
+  else launch<false>(s, nblocks, threads, smem, probs, st, bmap, twd, twf, ev0, ev1);
 }
 }  // namespace gpe

@@ -383,8 +383,14 @@ struct OOps {
 // one batch of loads: the trial point's arrays, the accumulator of the
 // earlier passes, the potential, the twiddle table and (final pass) the
 // first pass's norm partials.
+// RR (epilogue roles): the epilogue reads the trial point's inputs again,
+// half of the elements at a time, with the accumulator and the potential
+// (cache hits: the workgroup read the inputs before its transforms), instead
+// of holding them in registers through the transforms.  That takes the final
+// pass from one wavefront per SIMD to two, which pays where the launch has
+// enough tiles to be bandwidth bound and costs a little latency where not.
 // ---------------------------------------------------------------------------
-template <int N, int ROLE, typename CT, class Ops>
+template <int N, int ROLE, typename CT, class Ops, bool RR>
 __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState& S, int tile, const Ops& ops,
                                             cx<CT>* lds, const cx<CT>* tw1024, double* red) {
   constexpr int E = Tile<N>::E;
@@ -397,12 +403,13 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   typename Ops::In in[E];
   cx<CT> tv[E];
   double vp[E];
+  constexpr bool LATE = EPI && RR;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     in[e] = ops.load(T.g(e));
-    if constexpr (HAS_T) tv[e] = ld<CT>(P.t, T.g(e));
+    if constexpr (HAS_T && !LATE) tv[e] = ld<CT>(P.t, T.g(e));
   }
-  if constexpr (EPI) T.pot_load(P, vp);
+  if constexpr (EPI && !LATE) T.pot_load(P, vp);
   double c = 1.0, n_hat = 1.0;
   if constexpr (ROLE == R_FINAL) {
     // every wavefront reduces the first pass's norm partials itself
@@ -453,13 +460,26 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
       if (T.inner(e)) stc<CT>(P.t, T.g(e), tv[e] + v[e]);
   } else {
     AccF af;
+    constexpr int G = LATE ? 2 : 1;          // element groups of the epilogue
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (T.inner(e)) {
-        cx<double> kin = cvt<double>(v[e]);
-        if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
-        ops.final_(in[e], T.g(e), T.pot_value(P, vp[e]), kin, c, n_hat, af);
+    for (int hh = 0; hh < G; ++hh) {
+      if constexpr (LATE) {
+        __builtin_amdgcn_sched_barrier(0);    // keep the groups' loads apart
+#pragma unroll
+        for (int e = hh * (E / G); e < (hh + 1) * (E / G); ++e) {
+          in[e] = ops.load(T.g(e));
+          if constexpr (HAS_T) tv[e] = ld<CT>(P.t, T.g(e));
+          vp[e] = P.has_v ? gld<double>(P.v_arr, T.g(e)) : gld<double>(P.v_axis, ax * kMaxN + T.idx(e));
+        }
       }
+#pragma unroll
+      for (int e = hh * (E / G); e < (hh + 1) * (E / G); ++e)
+        if (T.inner(e)) {
+          cx<double> kin = cvt<double>(v[e]);
+          if constexpr (HAS_T) kin = kin + cvt<double>(tv[e]);
+          ops.final_(in[e], T.g(e), T.pot_value(P, vp[e]), kin, c, n_hat, af);
+        }
+    }
     double acc[SF_COUNT];
 #pragma unroll
     for (int i = 0; i < SF_COUNT_SUM; ++i) acc[i] = af.s[i];
@@ -527,26 +547,27 @@ __device__ __forceinline__ void pin_desc_fields(ProbDev& P) {
 }
 
 // Dispatch on the problem's mode.  PREC64: every array float64.
-template <int N, int ROLE, bool PREC64>
+template <int N, int ROLE, bool PREC64, bool RR>
 __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverState& S, int tile, char* smem,
                                                 const cx<double>* twd, const cx<float>* twf, double* red) {
   using TS = typename std::conditional<PREC64, double, float>::type;   // F/W storage and transforms
   const cx<TS>* tws = PREC64 ? reinterpret_cast<const cx<TS>*>(twd) : reinterpret_cast<const cx<TS>*>(twf);
   if (S.mode == M_F) {
     FOps<TS> ops(P, S);
-    solver_tile<N, ROLE, TS>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
+    solver_tile<N, ROLE, TS, FOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_W) {
     WOps<TS> ops(P, S);
-    solver_tile<N, ROLE, TS>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
+    solver_tile<N, ROLE, TS, WOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_OUTER) {
     OOps<TS, TS> ops(P, S);
-    solver_tile<N, ROLE, double>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd, red);
+    solver_tile<N, ROLE, double, OOps<TS, TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd,
+                                                   red);
   }
 }
 
 // `bmap` maps a workgroup to (problem, tile); null for a single problem
-// (workgroup b is tile b of problem 0).
-template <int ROLE, bool PREC64>
+// (workgroup b is tile b of problem 0).  RR: see solver_tile.
+template <int ROLE, bool PREC64, bool RR>
 __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__ probs,
                                                      SolverState* __restrict__ states,
                                                      const int2* __restrict__ bmap,
@@ -565,13 +586,13 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   if (S.mode == M_IDLE) return;
   const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   switch (n) {
-    case 16: solver_dispatch<16, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
-    case 32: solver_dispatch<32, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
-    case 64: solver_dispatch<64, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
-    case 128: solver_dispatch<128, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
-    case 256: solver_dispatch<256, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
-    case 512: solver_dispatch<512, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
-    case 1024: solver_dispatch<1024, ROLE, PREC64>(P, S, bm.y, smem, twd, twf, red); break;
+    case 16: solver_dispatch<16, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    case 32: solver_dispatch<32, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    case 64: solver_dispatch<64, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    case 128: solver_dispatch<128, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    case 256: solver_dispatch<256, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    case 512: solver_dispatch<512, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    case 1024: solver_dispatch<1024, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
     default: break;
   }
   if constexpr (ROLE == R_FINAL || ROLE == R_SOLO)
