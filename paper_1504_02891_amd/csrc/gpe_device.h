@@ -382,13 +382,13 @@ __device__ __forceinline__ void wave_reduce_k(double* acc, unsigned maxmask) {
 // s < NSLOT (a max where bit s of `maxmask` is set, else a sum), by one
 // wavefront: lane l accumulates i = l, l+64, l+128, ... in turn, then the
 // lanes are combined by wave_reduce_k.  Loads go out in batches of B per
-// lane (indices clamped, the extra values discarded).  Every lane of the
-// calling wavefront gets the result; every caller reducing the same
-// partials gets the same bits.
-template <int NSLOT>
+// lane (indices clamped, the extra values discarded; BB > 0 sets B).  Every
+// lane of the calling wavefront gets the result; every caller reducing the
+// same partials gets the same bits, whatever B and NSLOT.
+template <int NSLOT, int BB = 0>
 __device__ __forceinline__ void wave_reduce_partials(const double* part, int count, unsigned maxmask,
                                                      double* acc) {
-  constexpr int B = NSLOT <= 4 ? 8 : 4;
+  constexpr int B = BB > 0 ? BB : (NSLOT <= 4 ? 8 : 4);
   const int l = threadIdx.x & 63;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) acc[s] = 0.0;

@@ -5,21 +5,23 @@
 
 namespace gpe {
 
-// Scalar step as its own launch (one wavefront per problem).  The state is
+// Scalar step as its own launch (one workgroup per problem): the partial
+// sums are reduced by the workgroup's wavefronts, slot by slot; the state is
 // copied in with one batch of loads, advanced in registers by one thread and
 // written back whole.
-__global__ void __launch_bounds__(64) k_step(const ProbDev* __restrict__ probs, SolverState* __restrict__ states,
-                                             int prec64) {
+constexpr int kStepThreads = 512;
+__global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict__ probs,
+                                                       SolverState* __restrict__ states, int prec64) {
+  __shared__ double red[S1_COUNT + SF_COUNT];
   ProbDev P = probs[blockIdx.x];
   pin_reg(P.part1); pin_reg(P.partF); pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
   pin_reg(P.dim); pin_reg(P.sqrt_hvol);
-  SolverState L = states[blockIdx.x];
-  touch_lines(states + blockIdx.x);
-  if (L.mode == M_IDLE) return;
+  if (states[blockIdx.x].mode == M_IDLE) return;
+  if (threadIdx.x < 64) touch_lines(states + blockIdx.x);
   double r1[S1_COUNT], rf[SF_COUNT];
-  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], 1u << S1_RMAX, r1);
-  wave_reduce_partials<SF_COUNT>(P.partF, pick3(P.tiles, P.dim - 1), 1u << SF_SMAX, rf);
+  step_reductions(P.part1, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red);
   if (threadIdx.x == 0) {
+    SolverState L = states[blockIdx.x];
     step_logic(P, L, r1, rf, prec64);
     states[blockIdx.x] = L;
   }
@@ -297,7 +299,7 @@ __global__ void __launch_bounds__(256) k_prolong_axis(const cx<double>* __restri
 // launchers
 // ---------------------------------------------------------------------------
 void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64) {
-  hipLaunchKernelGGL(k_step, dim3(nprob), dim3(64), 0, s, probs, st, prec64);
+  hipLaunchKernelGGL(k_step, dim3(nprob), dim3(kStepThreads), 0, s, probs, st, prec64);
 }
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64) {
   const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);

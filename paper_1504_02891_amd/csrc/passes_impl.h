@@ -187,6 +187,40 @@ __device__ __forceinline__ double wave_reduce_slot(const double* part, int count
   wave_reduce_partials<1>(part + (int64_t)slot * count, count, is_max ? 1u : 0u, a);
   return a[0];
 }
+// The scalar step's reductions spread over the calling workgroup's
+// wavefronts: wavefront w reduces slots w, w + nw, ... of the first-pass (S1)
+// and final-pass (SF) partials, each slot in the fixed order of the
+// one-wavefront reduction (the same bits), and thread 0 gets r1 and rf
+// through `red` (at least S1_COUNT + SF_COUNT doubles).  Every thread of the
+// workgroup must call it (barrier).
+__device__ __forceinline__ void step_reductions(const double* part1, int n1, const double* partF, int nF,
+                                                double* r1, double* rf, double* red) {
+  constexpr int NS = S1_COUNT + SF_COUNT, BS = 32;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+  // rounds of dependent loads: one wavefront with every slot's loads in
+  // flight together (B = 4 per slot), or slot by slot over the wavefronts
+  // with BS loads per lane
+  const int cnt = max(n1, nF);
+  const bool spread = ((NS + nw - 1) / nw) * ((cnt + 64 * BS - 1) / (64 * BS)) < (cnt + 255) / 256;
+  if (spread) {
+    for (int k = w; k < NS; k += nw) {
+      double r[1];
+      if (k < S1_COUNT) wave_reduce_partials<1, BS>(part1 + (int64_t)k * n1, n1, k == S1_RMAX ? 1u : 0u, r);
+      else wave_reduce_partials<1, BS>(partF + (int64_t)(k - S1_COUNT) * nF, nF, k - S1_COUNT == SF_SMAX ? 1u : 0u, r);
+      if ((threadIdx.x & 63) == 0) red[k] = r[0];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int s = 0; s < S1_COUNT; ++s) r1[s] = red[s];
+#pragma unroll
+      for (int s = 0; s < SF_COUNT; ++s) rf[s] = red[S1_COUNT + s];
+    }
+  } else if (threadIdx.x < 64) {
+    wave_reduce_partials<S1_COUNT>(part1, n1, 1u << S1_RMAX, r1);
+    wave_reduce_partials<SF_COUNT>(partF, nF, 1u << SF_SMAX, rf);
+  }
+}
 // Fixed-order reduction for a whole workgroup: the first wavefront reduces,
 // every thread gets the result through `red`.
 template <int NSLOT>
@@ -511,11 +545,10 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, 
     is_last = last;
   }
   __syncthreads();
-  if (!is_last || threadIdx.x >= 64) return;
-  touch_lines(Sg);
+  if (!is_last) return;
+  if (threadIdx.x < 64) touch_lines(Sg);
   double r1[S1_COUNT], rf[SF_COUNT];
-  wave_reduce_partials<S1_COUNT>(P.part1, P.tiles[0], 1u << S1_RMAX, r1);
-  wave_reduce_partials<SF_COUNT>(P.partF, ntiles, 1u << SF_SMAX, rf);
+  step_reductions(P.part1, P.tiles[0], P.partF, ntiles, r1, rf, red);
   if (threadIdx.x == 0) {
     SolverState L = *Sg;
     step_logic(P, L, r1, rf, prec64);
