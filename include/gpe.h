@@ -266,6 +266,20 @@ int gpe_autotune(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, int32
                  int32_t* step_at_out, double* us_per_eval_out);
 
 /*
+ * Keep a given launch plan for the grid of `prob` and `precision` in the
+ * context, as gpe_autotune keeps the plan it picks (replacing an earlier one):
+ * for instance a plan recorded from an earlier gpe_autotune call, so that
+ * later runs tile the grid the same way and take the same bits.
+ * threads: HOST int32[3], the workgroup size of the x, y, z passes (entries
+ * beyond the problem's dimension ignored), each 64, 128 or 256 and a multiple
+ * of the pass's threads per line (the transform length / 8); step_at:
+ * GPE_STEP_LAST_GROUP or GPE_STEP_KERNEL.  GPE_EINVAL for anything else.
+ * Host only: no device work.
+ */
+int gpe_set_plan(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, const int32_t* threads,
+                 int32_t step_at);
+
+/*
  * Trigonometric prolongation for the cascadic multigrid (Algorithm 3): the
  * coarse grid function (n points per axis) is interpolated to 2n points per
  * axis on the same box (coarse points are every other fine point); per axis

@@ -34,7 +34,7 @@ GPE_STOP_CRIT2 = 2
 
 EXPORTS = ("gpe_ctx_create", "gpe_ctx_destroy", "gpe_options_default", "gpe_strerror",
            "gpe_last_error", "gpe_apply_h", "gpe_hess_vec", "gpe_retract", "gpe_solve",
-           "gpe_solve_batched", "gpe_prolong", "gpe_solve_cascadic", "gpe_autotune")
+           "gpe_solve_batched", "gpe_prolong", "gpe_solve_cascadic", "gpe_autotune", "gpe_set_plan")
 
 
 class Problem(C.Structure):
@@ -107,6 +107,7 @@ def lib():
                                     C.POINTER(Result)]
     L.gpe_prolong.argtypes = [vp, C.POINTER(Problem), C.POINTER(Problem), vp, vp]
     L.gpe_autotune.argtypes = [vp, C.POINTER(Problem), i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)]
+    L.gpe_set_plan.argtypes = [vp, C.POINTER(Problem), i32, C.POINTER(i32), i32]
     L.gpe_solve_cascadic.argtypes = [vp, i32, C.POINTER(Problem), i32, dbl, C.POINTER(Options),
                                      C.POINTER(vp), C.POINTER(vp), C.POINTER(Result)]
     for name in EXPORTS:

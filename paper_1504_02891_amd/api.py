@@ -206,6 +206,15 @@ def autotune(p, precision="mixed", device=0):
     return {"threads": list(thr), "step_at": step.value, "us_per_eval": us.value}
 
 
+def set_plan(p, precision, threads, step_at, device=0):
+    """Keep a given launch plan (e.g. one returned by ``autotune`` earlier) for
+    the grid of ``p`` in the device's context, as ``autotune`` keeps its own."""
+    prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
+    thr = (C.c_int32 * 3)(*[int(t) for t in list(threads)[:3]])
+    ps = problem_struct(p)
+    _check(N.lib().gpe_set_plan(context(device), C.byref(ps), prec, thr, int(step_at)), "gpe_set_plan")
+
+
 def prolong(p_coarse, p_fine, phi_c):
     _dev_tensor(phi_c, torch.complex128, "phi_c", p_coarse)
     shape = tuple(int(n) for n in reversed(p_fine.n[: p_fine.dim]))

@@ -406,6 +406,13 @@ const TunedPlan* find_plan(const gpe_ctx* c, const gpe_problem& p, int prec) {
   return nullptr;
 }
 
+// Keep plan `tp` for the grid of `p` (and tp.prec), replacing an earlier one.
+void keep_plan(gpe_ctx* c, const gpe_problem& p, const TunedPlan& tp) {
+  for (TunedPlan& t : c->plans)
+    if (find_plan(c, p, tp.prec) == &t) { t = tp; return; }
+  c->plans.push_back(tp);
+}
+
 // delta0 (optional): per-problem initial regularisation delta (an FP64
 // continuation keeps the delta its mixed-precision run reached)
 int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
@@ -1007,6 +1014,29 @@ int gpe_solve_batched(gpe_ctx* c, int32_t count, const gpe_problem* probs, const
   return solve_switch(c, count, probs, opts, phis, results);
 }
 
+int gpe_set_plan(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const int32_t* threads,
+                 int32_t step_at) {
+  if (!c || !prob || !threads) return GPE_EINVAL;
+  if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
+  if (step_at != GPE_STEP_LAST_GROUP && step_at != GPE_STEP_KERNEL) return GPE_EINVAL;
+  ProbDev d;
+  CHK(build_prob(prob, &d, nullptr));
+  TunedPlan tp{};
+  for (int a = 0; a < 3; ++a) {
+    if (a >= d.dim) continue;
+    const int tl = d.nl[a] / kE, t = threads[a];
+    if ((t != 64 && t != 128 && t != 256) || t < tl || t % tl != 0) return GPE_EINVAL;
+    tp.threads[a] = t;
+  }
+  tp.step_at = step_at;
+  tp.dim = prob->dim;
+  tp.bc = prob->bc;
+  tp.prec = precision;
+  for (int a = 0; a < 3; ++a) tp.n[a] = a < prob->dim ? prob->n[a] : 0;
+  keep_plan(c, *prob, tp);
+  return GPE_OK;
+}
+
 int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t* threads_out,
                  int32_t* step_at_out, double* us_per_eval_out) {
   if (!c || !prob) return GPE_EINVAL;
@@ -1079,10 +1109,7 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
   bp.bc = prob->bc;
   bp.prec = precision;
   for (int a = 0; a < 3; ++a) bp.n[a] = a < prob->dim ? prob->n[a] : 0;
-  bool replaced = false;
-  for (TunedPlan& t : c->plans)
-    if (find_plan(c, *prob, precision) == &t) { t = bp; replaced = true; }
-  if (!replaced) c->plans.push_back(bp);
+  keep_plan(c, *prob, bp);
   if (threads_out)
     for (int a = 0; a < 3; ++a) threads_out[a] = bp.threads[a];
   if (step_at_out) *step_at_out = bp.step_at;

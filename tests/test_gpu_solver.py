@@ -475,6 +475,24 @@ def test_rotating_3d_small(dev, prec):
     _compare(p, phi, ref.x, 1e-7, 1e-8, 1e-5)
 
 
+def test_set_plan(dev):
+    # a plan given to the context is used by later solves with open launch
+    # options: bitwise the same as passing it explicitly (a grid no other test
+    # uses, since the plan stays in the context); invalid plans are refused
+    from paper_1504_02891_amd.api import GpeError
+    p = W.Problem(dim=2, n=(128, 32), lo=(-10.0, -6.0), hi=(10.0, 6.0), beta=300.0, omega=0.2)
+    phi0 = W.rotating_initial(p, 0.2, 13)
+    dev.set_plan(p, "fp64", [64, 64, 0], 1)
+    phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="fp64")
+    phi_b, rb = _gpu_solve(dev, p, phi0, tol=1e-8, precision="fp64", threads=[64, 64, 0], step_at="kernel")
+    assert ra["status"] == 0 and ra["nfe"] == rb["nfe"]
+    assert np.array_equal(phi_a, phi_b)
+    for thr, sa in (([32, 64, 0], 1), ([64, 96, 0], 1), ([64, 64, 0], 5)):
+        with pytest.raises(GpeError) as e:
+            dev.set_plan(p, "fp64", thr, sa)
+        assert e.value.status == -1
+
+
 def test_autotune_plan(dev):
     # the tuned plan is a valid configuration, and a later solve with open
     # launch options uses it: bitwise the same as the plan given explicitly
