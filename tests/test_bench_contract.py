@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -14,3 +16,40 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2, (r.returncode, r.stderr[-2000:])
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_recorded_plans_are_valid():
+    # every recorded launch plan names a precision, a grid and a discretization,
+    # and passes the checks gpe_set_plan makes (64, 128 or 256 threads per
+    # pass, a multiple of the pass's threads per line, a fixed step placement)
+    plans = json.load(open(os.path.join(ROOT, "profiles", "launch_plans_mi355x.json")))["plans"]
+    assert plans
+    for key, plan in plans.items():
+        prec, grid, bc = key.split()
+        assert prec in ("mixed", "fp64") and bc == "fourier", key
+        n = [int(v) for v in grid.split("x")]
+        assert plan["step_at"] in (0, 1), key
+        for a, na in enumerate(n):
+            t, tl = plan["threads"][a], na // 8
+            assert t in (64, 128, 256) and t >= tl and t % tl == 0, (key, a, t)
+
+
+def test_recorded_traffic_weights_the_instances(tmp_path, monkeypatch):
+    # the roofline's traffic is the evaluation-weighted mean of the two pass
+    # instances' records, and null when a record needed is missing or stale
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = {}
+    for prec in ("mixed", "fp64"):
+        path = os.path.join(ROOT, "profiles", f"final_pass_rot2d_256_{prec}_traffic.json")
+        if not os.path.exists(path):
+            pytest.skip(f"no traffic record for {prec}")
+        rec[prec] = json.load(open(path))["traffic_bytes_per_launch"]
+    t32, t64 = bench.recorded_traffic("rot2d", 100, 0), bench.recorded_traffic("rot2d", 0, 100)
+    if t32 is None or t64 is None:
+        pytest.skip("the kernel sources changed since the counters were taken")
+    assert t32 == round(rec["mixed"]) and t64 == round(rec["fp64"])
+    assert bench.recorded_traffic("rot2d", 100, 300) == round((rec["mixed"] + 3 * rec["fp64"]) / 4)
+    assert bench.recorded_traffic("lattice3d", 100, 300) is None
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.recorded_traffic("rot2d", 100, 300) is None
