@@ -141,9 +141,10 @@ typedef struct gpe_options {
                              evaluation is below switch_resid but not yet below tol, the outer
                              iterate X_k starts an FP64 run of Algorithm 2 (its K_init steps of
                              Algorithm 1 first, the regularisation delta kept) with the remaining
-                             Newton steps: the Newton
-                             subproblems in FP32 stall near the FP32 residual floor.  0 = never
-                             (default 1e-4, about ten times the floor of the benchmark grids) */
+                             Newton steps (in a batch: the budget left to the problem that used
+                             the most), since the Newton subproblems in FP32 stall near the FP32
+                             residual floor.  0 = never (default 1e-4, about ten times the floor
+                             of the benchmark grids) */
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */
