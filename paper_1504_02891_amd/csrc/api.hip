@@ -633,8 +633,10 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   bool capturing = false;
   auto enqueue_eval = [&](int k) {
     // final pass: the epilogue re-reads its inputs once the launch has enough
-    // tiles to be bandwidth bound (four workgroups per compute unit)
-    const int reread = (int64_t)bm[dim - 1].size() >= kRereadTiles ? 1 : 0;
+    // tiles to be bandwidth bound (four workgroups per compute unit) and the
+    // tiles are two wavefronts or more (measured: 128^3 with 128-thread tiles
+    // 68 -> 49 us per launch; a batch of 64-thread tiles 129 -> 146 us)
+    const int reread = ((int64_t)bm[dim - 1].size() >= kRereadTiles && thr[dim - 1] >= 128) ? 1 : 0;
     const bool prof = sampled(eval_index++);
     const bool nodes = prof && capturing;                    // event record nodes around the pass
     hipEvent_t e0 = prof && !capturing ? pev[2 * k] : nullptr, e1 = prof && !capturing ? pev[2 * k + 1] : nullptr;
