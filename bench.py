@@ -327,7 +327,8 @@ def main():
         "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(1e3 * dt / a.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 bulk + f64 reductions/state" if a.precision == "mixed" else "f64",
+        "dtype": ("f32 bulk + f64 reductions/state, then f64 from the handover residual" if a.precision == "mixed"
+                  else "f64"),
         "data": "synthetic (seeded initial data of the paper's rotating/lattice workloads)",
         "config": {"workload": desc, "precision": a.precision, "tol": a.tol, "problems": len(probs),
                    "grid_points": pts},
