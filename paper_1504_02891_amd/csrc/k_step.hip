@@ -185,20 +185,28 @@ __global__ void __launch_bounds__(kSumThreads) k_apply_finalize(const ProbDev* p
                                                                 const double* __restrict__ rpart, int nr,
                                                                 double* __restrict__ out) {
   __shared__ double red[SR_COUNT * 16];
+  __shared__ double tl[SA_COUNT * kSumChunks];
   const ProbDev& P = probs[0];
+  // the chunk totals go out with the residual partials' loads (one each for
+  // the first threads) and reach thread 0 through LDS
+  constexpr int NT = SA_COUNT * kSumChunks;
+  double tv = 0.0;
+  if (threadIdx.x < NT) tv = tot[threadIdx.x];
   double acc[SR_COUNT];
   block_sum_partials<SR_COUNT_SUM, 2>(rpart, nr, acc, red);
+  if (threadIdx.x < NT) tl[threadIdx.x] = tv;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double e = apply_energy(P, tot), epot = P.hvol * slot_total(tot, SA_POT);
+    const double e = apply_energy(P, tl), epot = P.hvol * slot_total(tl, SA_POT);
     out[0] = e;
-    out[1] = apply_mu(P, tot);
+    out[1] = apply_mu(P, tl);
     out[2] = sqrt(acc[SR_RES]);
     out[3] = P.hvol * acc[SR_NORM];
     out[4] = sqrt(P.hvol * acc[SR_X2]);
     out[5] = sqrt(P.hvol * acc[SR_Y2]);
     out[6] = sqrt(P.hvol * acc[SR_Z2]);
     out[7] = acc[SR_MAXD];
-    out[8] = e - epot - 0.5 * P.beta * P.hvol * slot_total(tot, SA_QUART);
+    out[8] = e - epot - 0.5 * P.beta * P.hvol * slot_total(tl, SA_QUART);
     out[9] = epot;
   }
 }
