@@ -70,14 +70,18 @@ class FGResult:
 
 
 def feasible_gradient(fun, x, f, g, *, maxit, tau_init, stop, rho1=1e-4, eta=0.85,
-                      sigma=0.5, m_max=20, renorm_tol=1e-14, stats=None, stop_step=None):
+                      sigma=0.5, m_max=20, renorm_tol=1e-14, stats=None, stop_step=None,
+                      trace=None):
     """Algorithm 1 from the feasible point ``x`` with f(x), grad f(x) given.
 
     ``fun(Y) -> (f, G)``; ``stop(x, f, g, P) -> bool`` is tested on every
     iterate before a step is taken; ``stop_step(x_new, x_old, t) -> bool``
     (optional) right after each accepted step of length t (the paper's
     step-length rules).  eta = 0 makes the search monotone: C is then
-    f(X_k) itself.  Returns an ``FGResult``."""
+    f(X_k) itself.  ``trace`` (optional, for tests): a list that receives one
+    dict per accepted step with the iterate, its f, g and P, the BB step used,
+    the accepted trial length t, the backtracks m and the reference value C
+    and weight Q after the update.  Returns an ``FGResult``."""
     if stats is None:
         stats = FGStats()
     nx, a = re_dot(x, x), re_dot(x, g)
@@ -123,5 +127,8 @@ def feasible_gradient(fun, x, f, g, *, maxit, tau_init, stop, rho1=1e-4, eta=0.8
         Q = Qn
         k += 1
         stats.iters += 1
+        if trace is not None:
+            trace.append({"k": k, "x": x, "f": f, "g": g, "P": P, "tau_bb": tau_bb, "t": t,
+                          "m": m, "C": C, "Q": Q})
         if stop_step is not None and stop_step(x, x_prev, t):
             return FGResult(x, f, g, tau_bb, True, k)

@@ -119,6 +119,23 @@ def feasible_only(up, x0, opts: Options):
     return SolveResult(res.x, res.stopped, 0, st.iters, st.nfe, st.backtracks)
 
 
+def actual_reduction(up, xk, gk, z):
+    """F(Z) - F(X_k) in difference form (the numerator of the ratio rho, §3.2).
+
+    With S = Z - X_k, A X_k = G_k - 4 alpha |X_k|^2 X_k and
+    |Z|^4 - |X_k|^4 = (|Z|^2 - |X_k|^2)(|Z|^2 + |X_k|^2),
+    |Z|^2 - |X_k|^2 = 2 Re(conj(X_k) S) + |S|^2, the difference of the two
+    energies is a sum of terms that vanish with S, so it keeps its relative
+    accuracy when F(Z) and F(X_k) agree to many digits."""
+    alpha = up.alpha
+    s = z - xk
+    qk = np.abs(xk) ** 2
+    axk = gk - 4.0 * alpha * qk * xk
+    return (re_dot(s, axk) + 0.5 * re_dot(s, up.A(s))
+            + alpha * float(np.sum((2.0 * np.real(np.conj(xk) * s) + np.abs(s) ** 2)
+                                   * (np.abs(z) ** 2 + qk))))
+
+
 def regularized_newton(up, x0, opts: Options, log=False):
     """Algorithm 2 from x0 (need not be normalised)."""
     o = opts
@@ -174,12 +191,8 @@ def regularized_newton(up, x0, opts: Options, log=False):
             stats=st, **_fg_kwargs(o))
         tau = inner.tau_bb
         z = inner.x
-        s = z - xk
         pred = inner.f
-        axk = gk - 4.0 * alpha * qk * xk
-        ared = (re_dot(s, axk) + 0.5 * re_dot(s, up.A(s))
-                + alpha * float(np.sum((2.0 * np.real(np.conj(xk) * s) + np.abs(s) ** 2)
-                                       * (np.abs(z) ** 2 + qk))))
+        ared = actual_reduction(up, xk, gk, z)
         rho = ared / pred if pred < 0.0 else -math.inf
         if rho >= o.eta1:
             x_prev = x
