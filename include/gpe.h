@@ -72,11 +72,16 @@ extern "C" {
 #define GPE_STOP_CRIT2       2
 
 /* Placement of the scalar step (line search / trust-region update) that
-   follows each evaluation; results do not depend on it. */
+   follows each evaluation; results do not depend on it (every placement
+   reduces the same partial sums in the same order). */
 #define GPE_STEP_AUTO       -1   /* LAST_GROUP when the final pass has at most 128 workgroups
                                     per problem (always in 1D), else KERNEL */
 #define GPE_STEP_LAST_GROUP  0   /* last workgroup of the final pass (a device-scope fence per workgroup) */
 #define GPE_STEP_KERNEL      1   /* a launch of its own after the final pass */
+#define GPE_STEP_FUSED       2   /* at the start of the next evaluation's first pass, by every
+                                    workgroup of that pass on its own copy of the state (two
+                                    or three launches per evaluation instead of three or four;
+                                    dim >= 2, else LAST_GROUP; the chunk is rounded up to even) */
 
 /* ---- problem ------------------------------------------------------------ */
 typedef struct gpe_problem {
@@ -214,21 +219,29 @@ int gpe_apply_h(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision,
 /*
  * Hessian-vector product of the regularized Newton model (Lemma 3.1, §3.2),
  * in X units:  out = A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s.
- * x_k, s, out: DEVICE complex128 arrays (out may not alias the inputs).
+ *   precision  GPE_PREC_FP64: s and out complex128, transforms in float64;
+ *              GPE_PREC_MIXED: s and out complex64, transforms of s in
+ *              float32, the pointwise terms in float64 rounded to float32 on
+ *              store (the solver's Newton passes in mixed precision).
+ *   x_k        DEVICE complex128 in both precisions (the outer iterate stays
+ *              float64); s, out DEVICE (out may not alias the inputs).
  */
-int gpe_hess_vec(gpe_ctx* ctx, const gpe_problem* prob, const void* x_k, const void* s,
-                 double delta, void* out);
+int gpe_hess_vec(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, const void* x_k,
+                 const void* s, double delta, void* out);
 
 /*
  * Cayley retraction (§3.1, Theorem 3.3) in the real reading: with
  * a = Re(x^* g), n_x = ||x||^2, n_g = ||g||^2,
  *   y = p x + q g,  p = ((1 + tau a)^2 - tau^2 n_x n_g)/den,  q = -2 tau n_x/den,
  *   den = 1 - tau^2 a^2 + tau^2 n_x n_g.
- * x, g, y: DEVICE complex128 arrays of m elements (y may alias neither).
- * coeffs: HOST double[5] out or NULL: p, q, a, n_x, n_g.  Blocks.
+ *   precision  GPE_PREC_FP64: x, g, y complex128; GPE_PREC_MIXED: complex64
+ *              (a, n_x, n_g summed and p, q formed in float64 either way).
+ * x, g, y: DEVICE arrays of m elements (y may alias neither).
+ * coeffs: HOST double[5] out or NULL: p, q, a, n_x, n_g.  Blocks when coeffs
+ * is not NULL.
  */
-int gpe_retract(gpe_ctx* ctx, int64_t m, const void* x, const void* g, double tau,
-                void* y, double* coeffs);
+int gpe_retract(gpe_ctx* ctx, int64_t m, int32_t precision, const void* x, const void* g,
+                double tau, void* y, double* coeffs);
 
 /*
  * Ground state by Algorithm 1 or 2 (§3).  phi: DEVICE complex128 array; on
@@ -253,8 +266,9 @@ int gpe_solve_batched(gpe_ctx* ctx, int32_t count, const gpe_problem* probs,
 /*
  * Tuning of the launch configuration for one grid (dim, n, bc) and precision:
  * short solves of a synthetic state on that grid time every valid workgroup
- * size per pass (64, 128, 256 threads, a multiple of n/8) and both step
- * placements; the fastest plan is kept in the context (one per grid and
+ * size per pass (64, 128, 256 threads, a multiple of n/8) and every step
+ * placement (GPE_STEP_FUSED up to 512 first-pass workgroups, in 2D and 3D);
+ * the fastest plan is kept in the context (one per grid and
  * precision, replaced by a later call).  Later gpe_solve / gpe_solve_batched /
  * gpe_solve_cascadic calls on a context with a plan for their grid use it
  * wherever their options leave the choice open (threads 0, step_at AUTO).
@@ -274,7 +288,8 @@ int gpe_autotune(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, int32
  * threads: HOST int32[3], the workgroup size of the x, y, z passes (entries
  * beyond the problem's dimension ignored), each 64, 128 or 256 and a multiple
  * of the pass's threads per line (the transform length / 8); step_at:
- * GPE_STEP_LAST_GROUP or GPE_STEP_KERNEL.  GPE_EINVAL for anything else.
+ * GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL or GPE_STEP_FUSED.  GPE_EINVAL for
+ * anything else.
  * Host only: no device work.
  */
 int gpe_set_plan(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, const int32_t* threads,
@@ -298,6 +313,11 @@ int gpe_prolong(gpe_ctx* ctx, const gpe_problem* coarse, const gpe_problem* fine
  * all `count` problems, coarse levels to `level_tol`, the finest to opts->tol.
  * phi0s[i]: DEVICE complex128 initial data on the coarse grid (read only);
  * phis[i]: DEVICE complex128 outputs on the finest grid.  Fourier problems only.
+ * results[i]: the finest level's outputs (E, mu, residual, ...); every counter
+ * (iterations, evaluations by kind and precision, backtracks, rejections,
+ * switch_iter, profile samples, time) summed over the levels; the status is
+ * the worst of the levels' (a coarse level stopped at its cap reports
+ * GPE_NOT_CONVERGED).
  */
 int gpe_solve_cascadic(gpe_ctx* ctx, int32_t count, const gpe_problem* coarse,
                        int32_t nlevels, double level_tol, const gpe_options* opts,

@@ -28,6 +28,7 @@ GPE_ALG2 = 2
 GPE_STEP_AUTO = -1
 GPE_STEP_LAST_GROUP = 0
 GPE_STEP_KERNEL = 1
+GPE_STEP_FUSED = 2
 GPE_STOP_RESID = 0
 GPE_STOP_CRIT1 = 1
 GPE_STOP_CRIT2 = 2
@@ -100,8 +101,8 @@ def lib():
     L.gpe_last_error.argtypes = []
     L.gpe_last_error.restype = C.c_char_p
     L.gpe_apply_h.argtypes = [vp, C.POINTER(Problem), i32, vp, vp, C.POINTER(dbl)]
-    L.gpe_hess_vec.argtypes = [vp, C.POINTER(Problem), vp, vp, dbl, vp]
-    L.gpe_retract.argtypes = [vp, C.c_int64, vp, vp, dbl, vp, C.POINTER(dbl)]
+    L.gpe_hess_vec.argtypes = [vp, C.POINTER(Problem), i32, vp, vp, dbl, vp]
+    L.gpe_retract.argtypes = [vp, C.c_int64, i32, vp, vp, dbl, vp, C.POINTER(dbl)]
     L.gpe_solve.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), vp, C.POINTER(Result)]
     L.gpe_solve_batched.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(Options), C.POINTER(vp),
                                     C.POINTER(Result)]

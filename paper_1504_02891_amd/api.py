@@ -84,7 +84,7 @@ def options(**kw):
     step = kw.pop("step_at", None)
     if step is not None:
         o.step_at = {"auto": N.GPE_STEP_AUTO, "last_group": N.GPE_STEP_LAST_GROUP,
-                     "kernel": N.GPE_STEP_KERNEL}.get(step, step)
+                     "kernel": N.GPE_STEP_KERNEL, "fused": N.GPE_STEP_FUSED}.get(step, step)
     thr = kw.pop("threads", None)
     if thr is not None:
         for i, t in enumerate(list(thr)[:3]):
@@ -140,25 +140,35 @@ def apply_h(p, phi, precision="fp64", v=None, scalars=True, out=None):
     return out, (dict(zip(SCALAR_NAMES, list(sc))) if scalars else None)
 
 
-def hess_vec(p, x_k, s, delta, v=None):
-    """A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s (X units)."""
+def _prec(precision):
+    prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
+    return prec, (torch.complex128 if prec == N.GPE_PREC_FP64 else torch.complex64)
+
+
+def hess_vec(p, x_k, s, delta, v=None, precision="fp64"):
+    """A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s (X units).
+    x_k is complex128 in both precisions; s and the result are complex128
+    ("fp64") or complex64 ("mixed")."""
+    prec, dt = _prec(precision)
     _dev_tensor(x_k, torch.complex128, "x_k", p)
-    _dev_tensor(s, torch.complex128, "s", p)
+    _dev_tensor(s, dt, "s", p)
     out = torch.empty_like(s)
     ps = problem_struct(p, v)
-    _check(N.lib().gpe_hess_vec(context(s.device.index), C.byref(ps), C.c_void_p(x_k.data_ptr()),
+    _check(N.lib().gpe_hess_vec(context(s.device.index), C.byref(ps), prec, C.c_void_p(x_k.data_ptr()),
                                 C.c_void_p(s.data_ptr()), float(delta), C.c_void_p(out.data_ptr())),
            "gpe_hess_vec")
     return out
 
 
-def retract(x, g, tau):
-    """Cayley curve point y = p x + q g; returns (y, dict(p, q, a, nx, ng))."""
-    _dev_tensor(x, torch.complex128, "x")
-    _dev_tensor(g, torch.complex128, "g")
+def retract(x, g, tau, precision="fp64"):
+    """Cayley curve point y = p x + q g; returns (y, dict(p, q, a, nx, ng)).
+    x, g and y are complex128 ("fp64") or complex64 ("mixed")."""
+    prec, dt = _prec(precision)
+    _dev_tensor(x, dt, "x")
+    _dev_tensor(g, dt, "g")
     y = torch.empty_like(x)
     co = (C.c_double * 5)()
-    _check(N.lib().gpe_retract(context(x.device.index), x.numel(), C.c_void_p(x.data_ptr()),
+    _check(N.lib().gpe_retract(context(x.device.index), x.numel(), prec, C.c_void_p(x.data_ptr()),
                                C.c_void_p(g.data_ptr()), float(tau), C.c_void_p(y.data_ptr()), co),
            "gpe_retract")
     return y, dict(zip(("p", "q", "a", "nx", "ng"), list(co)))

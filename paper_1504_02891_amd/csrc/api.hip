@@ -34,6 +34,9 @@ thread_local std::string g_last_error;
 constexpr int kSolverThreads = 128;   // threads per workgroup of every solver pass
 constexpr int kApplyThreads = 128;
 constexpr int64_t kRereadTiles = 1024;  // final-pass tiles from which its epilogue re-reads (256 CUs x 4)
+// STEP_FUSED is tried by the autotuner only up to this many first-pass tiles
+// (every one of them reduces all partial sums of the previous evaluation)
+constexpr int64_t kFusedMaxTiles = 512;
 
 // Workspace slots owned by a context (grown on demand, freed at destroy).
 enum WsSlot {
@@ -345,7 +348,7 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
 // solver
 // ---------------------------------------------------------------------------
 struct ProbLayout {
-  size_t off_xf[2], off_gf[2], off_s[2], off_d[2], off_xk, off_gk, off_t, off_p1, off_pf, off_ticket;
+  size_t off_xf[2], off_gf[2], off_s[2], off_d[2], off_xk, off_gk, off_t, off_p1, off_p1x, off_pf, off_ticket;
 };
 
 void init_state(SolverState& S, const gpe_options& o) {
@@ -379,7 +382,7 @@ int check_options(const gpe_options* o) {
   if (!(o->sigma > 0.0 && o->sigma < 1.0) || !(o->eta >= 0.0 && o->eta < 1.0) || !(o->tau0 > 0.0))
     return GPE_EINVAL;
   if (o->chunk < 1 || o->chunk > 4096) return GPE_EINVAL;
-  if (o->step_at < GPE_STEP_AUTO || o->step_at > GPE_STEP_KERNEL) return GPE_EINVAL;
+  if (o->step_at < GPE_STEP_AUTO || o->step_at > GPE_STEP_FUSED) return GPE_EINVAL;
   if (o->real_field < -1 || o->real_field > 1) return GPE_EINVAL;
   if (o->stop_rule < GPE_STOP_RESID || o->stop_rule > GPE_STOP_CRIT2) return GPE_EINVAL;
   if (o->monotone != 0 && o->monotone != 1) return GPE_EINVAL;
@@ -492,8 +495,14 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     for (int i = 0; i < count; ++i) maxt = std::max(maxt, pd[i].tiles[dim - 1]);
     step_at = (dim == 1 || maxt <= 128) ? STEP_LAST_GROUP : STEP_KERNEL;
   }
+  // a 1D problem is one pass of one workgroup: its step ends that pass
+  if (dim == 1) step_at = STEP_LAST_GROUP;
   for (int i = 0; i < count; ++i) pd[i].step_at = step_at;
-  const int chunk = o.chunk;
+  const bool fused = step_at == STEP_FUSED;
+  // STEP_FUSED alternates two state arrays and two first-pass partials
+  // buffers by evaluation parity; an even chunk leaves the latest state in
+  // the first array at every host check
+  const int chunk = fused ? (o.chunk + 1) & ~1 : o.chunk;
   // arena layout
   std::vector<ProbLayout> lay(count);
   size_t off = 0;
@@ -515,6 +524,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     L.off_gk = take(m * 16);
     L.off_t = take(m * 16);
     L.off_p1 = take((size_t)pd[i].tiles[0] * S1_COUNT * sizeof(double));
+    L.off_p1x = take((size_t)pd[i].tiles[0] * S1_COUNT * sizeof(double));
     L.off_pf = take((size_t)std::max(pd[i].tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
     L.off_ticket = take(64);
   }
@@ -551,7 +561,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   void *arena, *dprob, *dstate, *dvax, *dbm[3] = {nullptr, nullptr, nullptr};
   CHK(ws_get(c, WS_ARENA, off, &arena));
   CHK(ws_get(c, WS_PROB, sizeof(ProbDev) * count, &dprob));
-  CHK(ws_get(c, WS_STATE, sizeof(SolverState) * count, &dstate));
+  CHK(ws_get(c, WS_STATE, 2 * sizeof(SolverState) * count, &dstate));
   CHK(ws_get(c, WS_VAXIS, vaxis.size() * sizeof(double), &dvax));
   char* A = (char*)arena;
   for (int i = 0; i < count; ++i) {
@@ -567,6 +577,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     d.gk = A + L.off_gk;
     d.t = A + L.off_t;
     d.part1 = (double*)(A + L.off_p1);
+    d.part1x = (double*)(A + L.off_p1x);
     d.partF = (double*)(A + L.off_pf);
     d.ticket = (int32_t*)(A + L.off_ticket);
     d.v_axis = (const double*)dvax + (size_t)i * 3 * kMaxN;
@@ -589,6 +600,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   CHK(upload(c, dprob, pd.data(), sizeof(ProbDev) * count, so));
   so += sizeof(ProbDev) * count;
   CHK(upload(c, dstate, st.data(), sizeof(SolverState) * count, so));
+  CHK(upload(c, (SolverState*)dstate + count, st.data(), sizeof(SolverState) * count, so));
   so += sizeof(SolverState) * count;
   for (int ax = 0; ax < dim; ++ax) {
     CHK(upload(c, dbm[ax], bm[ax].data(), bm[ax].size() * sizeof(int2), so));
@@ -641,16 +653,21 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     const bool nodes = prof && capturing;                    // event record nodes around the pass
     hipEvent_t e0 = prof && !capturing ? pev[2 * k] : nullptr, e1 = prof && !capturing ? pev[2 * k + 1] : nullptr;
     const int last = dim == 1 ? R_SOLO : R_FINAL;
+    // STEP_FUSED: the first pass reads the state of parity `par` and stores
+    // the stepped state in the other array, which the later passes read
+    const int par = fused ? (k & 1) : 0;
+    SolverState* s_in = S + (size_t)par * count;
+    SolverState* s_new = fused ? S + (size_t)(par ^ 1) * count : S;
     if (dim > 1) {
-      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, S, bmap(0), c->twd,
-                         c->twf);
+      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, s_in, s_new, bmap(0),
+                         c->twd, c->twf, par);
       if (dim == 3)
-        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, S, bmap(1), c->twd,
-                           c->twf);
+        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, s_new, s_new, bmap(1),
+                           c->twd, c->twf, par);
     }
     if (nodes) record(pev[2 * k]);
-    launch_solver_pass(c->s, last, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, S,
-                       bmap(dim - 1), c->twd, c->twf, e0, e1, reread);
+    launch_solver_pass(c->s, last, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, s_new, s_new,
+                       bmap(dim - 1), c->twd, c->twf, par, e0, e1, reread);
     if (nodes) record(pev[2 * k + 1]);
     if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S, prec64);
   };
@@ -855,7 +872,12 @@ int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_opti
   std::vector<gpe_result> r2(idx.size());
   const int rc2 = solve_impl(c, (int)idx.size(), sp.data(), &o2, sphi.data(), r2.data(),
                              opts->algorithm == GPE_ALG1 ? nullptr : d0.data());
-  if (rc2 < 0) return rc2;
+  if (rc2 < 0) {
+    // the handed-over problems carry the continuation's error, not the
+    // internal hand-over status
+    for (int i : idx) results[i].status = rc2;
+    return rc2;
+  }
   for (size_t k = 0; k < idx.size(); ++k) {
     gpe_result& a = results[idx[k]];
     gpe_result b = r2[k];
@@ -881,6 +903,24 @@ int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_opti
     else if (results[i].status == GPE_NOT_CONVERGED && worst == GPE_OK) worst = GPE_NOT_CONVERGED;
   }
   return worst;
+}
+
+// Statuses a caller may see: GPE_OK, GPE_NOT_CONVERGED or a documented
+// negative code.  The internal hand-over status never leaves the library
+// (solve_switch replaces it); anything else unexpected reads as not
+// converged.
+int public_status(int st) {
+  if (st == GPE_OK || st == GPE_NOT_CONVERGED) return st;
+  if (st <= GPE_EINVAL && st >= GPE_ENONFINITE) return st;
+  return GPE_NOT_CONVERGED;
+}
+
+int solve_public(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
+                 gpe_result* results) {
+  if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
+  const int rc = solve_switch(c, count, probs, opts, phis, results);
+  for (int i = 0; i < count; ++i) results[i].status = public_status(results[i].status);
+  return public_status(rc);
 }
 
 }  // namespace
@@ -979,22 +1019,26 @@ int gpe_apply_h(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const vo
   return end_call(c);
 }
 
-int gpe_hess_vec(gpe_ctx* c, const gpe_problem* prob, const void* x_k, const void* s, double delta, void* out) {
+int gpe_hess_vec(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const void* x_k, const void* s,
+                 double delta, void* out) {
   if (!c || !prob || !x_k || !s || !out || out == s || out == x_k) return GPE_EINVAL;
+  if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
   CHK(begin_call(c));
   ApplyArgs a{1, delta, s, x_k, out};
-  CHK(run_apply(c, prob, 1, a, nullptr));
+  CHK(run_apply(c, prob, precision == GPE_PREC_FP64, a, nullptr));
   return end_call(c);
 }
 
-int gpe_retract(gpe_ctx* c, int64_t m, const void* x, const void* g, double tau, void* y, double* coeffs) {
+int gpe_retract(gpe_ctx* c, int64_t m, int32_t precision, const void* x, const void* g, double tau, void* y,
+                double* coeffs) {
   if (!c || m < 1 || !x || !g || !y || y == x || y == g) return GPE_EINVAL;
+  if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
   CHK(begin_call(c));
   const int nblk = (int)std::min<int64_t>((m + 255) / 256, 1024);
   void* part;
   CHK(ws_get(c, WS_RETRACT, (size_t)nblk * 3 * sizeof(double) + 64, &part));
   double* coef_dev = (double*)part + (size_t)nblk * 3;
-  launch_retract(c->s, nblk, x, g, y, m, tau, (double*)part, coef_dev);
+  launch_retract(c->s, nblk, x, g, y, m, tau, (double*)part, coef_dev, precision == GPE_PREC_FP64);
   HIPCHK(hipGetLastError());
   if (coeffs) {
     void* pin;
@@ -1008,19 +1052,19 @@ int gpe_retract(gpe_ctx* c, int64_t m, const void* x, const void* g, double tau,
 
 int gpe_solve(gpe_ctx* c, const gpe_problem* prob, const gpe_options* opts, void* phi, gpe_result* result) {
   void* phis[1] = {phi};
-  return solve_switch(c, 1, prob, opts, phis, result);
+  return solve_public(c, 1, prob, opts, phis, result);
 }
 
 int gpe_solve_batched(gpe_ctx* c, int32_t count, const gpe_problem* probs, const gpe_options* opts,
                       void* const* phis, gpe_result* results) {
-  return solve_switch(c, count, probs, opts, phis, results);
+  return solve_public(c, count, probs, opts, phis, results);
 }
 
 int gpe_set_plan(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const int32_t* threads,
                  int32_t step_at) {
   if (!c || !prob || !threads) return GPE_EINVAL;
   if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
-  if (step_at != GPE_STEP_LAST_GROUP && step_at != GPE_STEP_KERNEL) return GPE_EINVAL;
+  if (step_at != GPE_STEP_LAST_GROUP && step_at != GPE_STEP_KERNEL && step_at != GPE_STEP_FUSED) return GPE_EINVAL;
   ProbDev d;
   CHK(build_prob(prob, &d, nullptr));
   TunedPlan tp{};
@@ -1088,7 +1132,8 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
   for (int t0 : cand[0])
     for (int t1 : cand[1])
       for (int t2 : cand[2])
-        for (int sa : {GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL}) {
+        for (int sa : {GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL, GPE_STEP_FUSED}) {
+          if (sa == GPE_STEP_FUSED && (d.dim == 1 || d.m / d.n[0] / (t0 / (d.nl[0] / kE)) > kFusedMaxTiles)) continue;
           o.threads[0] = t0; o.threads[1] = t1; o.threads[2] = t2;
           o.step_at = sa;
           double us = INFINITY;
@@ -1173,9 +1218,8 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
     HIPCHK(hipMemcpyAsync(cur[i], phi0s[i], m * 16, hipMemcpyDeviceToDevice, c->s));
   }
   CHK(end_call(c));
-  std::vector<gpe_result> tmp(count);
-  std::vector<int64_t> nfe(count, 0), nfe64(count, 0), outer(count, 0), inner(count, 0), nmix(3 * count, 0);
-  double tms = 0.0;
+  std::vector<gpe_result> tmp(count), tot(count);
+  for (int i = 0; i < count; ++i) std::memset(&tot[i], 0, sizeof(gpe_result));
   int rc = GPE_OK;
   for (int l = 0; l < nlevels; ++l) {
     gpe_options o = *opts;
@@ -1190,14 +1234,25 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
         HIPCHK(hipMemcpyAsync(phis[i], cur[i], m * 16, hipMemcpyDeviceToDevice, c->s));
         CHK(end_call(c));
       }
-    rc = solve_switch(c, count, lev.data(), &o, dst.data(), tmp.data());
-    if (rc < 0) return rc;
+    const int rl = solve_public(c, count, lev.data(), &o, dst.data(), tmp.data());
+    if (rl < 0) return rl;
+    // every counter adds up over the levels; the status is the worst one
+    // met on any level (a coarse level that stops at its cap is reported)
     for (int i = 0; i < count; ++i) {
-      nfe[i] += tmp[i].nfe; nfe64[i] += tmp[i].nfe_fp64;
-      outer[i] += tmp[i].outer_iters; inner[i] += tmp[i].inner_iters;
-      for (int k = 0; k < 3; ++k) nmix[3 * i + k] += tmp[i].nfe_mixed[k];
+      gpe_result& a = tot[i];
+      const gpe_result& b = tmp[i];
+      a.outer_iters += b.outer_iters; a.inner_iters += b.inner_iters;
+      a.nfe += b.nfe; a.nfe_fp64 += b.nfe_fp64;
+      a.backtracks += b.backtracks; a.rejections += b.rejections;
+      a.switch_iter += b.switch_iter;
+      a.nfe_f += b.nfe_f; a.nfe_w += b.nfe_w; a.nfe_outer += b.nfe_outer;
+      a.pass_launches += b.pass_launches; a.pass_ms += b.pass_ms;
+      for (int k = 0; k < 3; ++k) a.nfe_mixed[k] += b.nfe_mixed[k];
+      if (b.status < 0 && a.status >= 0) a.status = b.status;
+      else if (b.status == GPE_NOT_CONVERGED && a.status == GPE_OK) a.status = GPE_NOT_CONVERGED;
     }
-    tms += tmp[0].time_ms;
+    if (rl == GPE_NOT_CONVERGED) rc = GPE_NOT_CONVERGED;
+    tot[0].time_ms += tmp[0].time_ms;
     if (l < nlevels - 1) {
       for (int i = 0; i < count; ++i) {
         gpe_problem fine = lev[i];
@@ -1208,14 +1263,21 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
       std::swap(cur, nxt);
     }
   }
+  // outputs of the finest level, counters of all levels
   for (int i = 0; i < count; ++i) {
-    results[i] = tmp[i];
-    results[i].nfe = (int32_t)nfe[i];
-    results[i].nfe_fp64 = (int32_t)nfe64[i];
-    results[i].outer_iters = (int32_t)outer[i];
-    results[i].inner_iters = (int32_t)inner[i];
-    for (int k = 0; k < 3; ++k) results[i].nfe_mixed[k] = (int32_t)nmix[3 * i + k];
-    results[i].time_ms = tms;
+    gpe_result r = tmp[i];
+    const gpe_result& a = tot[i];
+    r.status = a.status;
+    r.outer_iters = a.outer_iters; r.inner_iters = a.inner_iters;
+    r.nfe = a.nfe; r.nfe_fp64 = a.nfe_fp64;
+    r.backtracks = a.backtracks; r.rejections = a.rejections;
+    r.switch_iter = a.switch_iter;
+    r.nfe_f = a.nfe_f; r.nfe_w = a.nfe_w; r.nfe_outer = a.nfe_outer;
+    r.pass_launches = a.pass_launches; r.pass_ms = a.pass_ms;
+    for (int k = 0; k < 3; ++k) r.nfe_mixed[k] = a.nfe_mixed[k];
+    r.time_ms = tot[0].time_ms;
+    results[i] = r;
+    if (r.status < 0 && rc >= 0) rc = r.status;
   }
   return rc;
 }

@@ -57,6 +57,21 @@ template <typename T> __device__ __forceinline__ void pin_reg(T& x) {
   }
 }
 
+// The value of `x` in the wavefront's first active lane, in a scalar
+// register: for values that are uniform but which the compiler cannot prove
+// uniform (read from LDS, for instance).
+template <typename T> __device__ __forceinline__ void make_uniform(T& x) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "make_uniform: 32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    x = __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+  } else {
+    const uint64_t w = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(w >> 32));
+    x = __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
 // One load per 64-byte line of a struct, all issued together and completed
 // here: later reads of any of its fields (issued lazily by the compiler, one
 // branch at a time) then hit the cache instead of each waiting on memory.

@@ -6,12 +6,15 @@
 #include "gpe_state.h"
 
 namespace gpe {
-// bmap: null for a single problem; ev0/ev1 (optional, plain launches only):
-// events stamped by the dispatch itself at the kernel's start and end;
-// reread (final and solo roles): the epilogue re-reads the trial inputs
+// bmap: null for a single problem; st_in/st_out: the state arrays read and
+// (STEP_FUSED, first pass) written; par: the evaluation's parity under
+// STEP_FUSED, else 0; ev0/ev1 (optional, plain launches only): events stamped
+// by the dispatch itself at the kernel's start and end; reread (final and
+// solo roles): the epilogue re-reads the trial inputs
 void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int threads, size_t smem,
-                        const ProbDev* probs, SolverState* st, const int2* bmap, const void* twd, const void* twf,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int reread = 0);
+                        const ProbDev* probs, SolverState* st_in, SolverState* st_out, const int2* bmap,
+                        const void* twd, const void* twf, int par, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                        int reread = 0);
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
 void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64);
@@ -25,8 +28,9 @@ void launch_apply_resid(hipStream_t s, int nblk, const ProbDev* probs, int nsum,
 // out[0..9]: the scalars of gpe_apply_h from tot and the residual maxima
 void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* tot, const double* rpart, int nr,
                            double* out);
+// fp64: complex128 x, g, y; else complex64 (reductions and coefficients in float64 either way)
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
-                    double* part, double* coeffs);
+                    double* part, double* coeffs, int fp64);
 // per-block max |Im x_i| of a complex128 array (part[nblk])
 void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* part);
 void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,

@@ -43,7 +43,9 @@ enum Mode : int32_t { M_IDLE = 0, M_F = 1, M_W = 2, M_OUTER = 3 };
 // Solver phases.
 enum Phase : int32_t { PH_INIT = 0, PH_ALG1 = 1, PH_OUTER = 2, PH_INNER = 3, PH_DONE = 4 };
 // Where the scalar step after an evaluation runs (see the GPE_STEP_* values).
-enum StepAt : int32_t { STEP_LAST_GROUP = 0, STEP_KERNEL = 1 };
+// STEP_FUSED: every workgroup of the next evaluation's first pass runs it on
+// its own (the same bits in each), before forming its trial point.
+enum StepAt : int32_t { STEP_LAST_GROUP = 0, STEP_KERNEL = 1, STEP_FUSED = 2 };
 
 // Internal status: mixed-precision Algorithm 1 stalled at the FP32 floor; the
 // host continues in FP64.
@@ -93,6 +95,7 @@ struct ProbDev {
   void* gk;              // G_k = grad F(X_k) (complex double)
   void* t;               // accumulator of the directional passes (complex double sized)
   double* part1;         // [S1_COUNT][tiles[0]] (slot-major)
+  double* part1x;        // second first-pass buffer (STEP_FUSED: evaluations alternate)
   double* partF;         // [SF_COUNT][tiles[dim-1]] (slot-major)
   int32_t* ticket;       // workgroups of the final pass done (reset by the last one)
   const void* user_in;   // apply / init input
@@ -124,7 +127,8 @@ struct SolverState {
   double best_r;                           // best residual of Algorithm 1 (stall test)
   double switch_r;                         // mixed Algorithm 2: FP64 handover residual
   int32_t k_init, k_sub, m_max, max_iter;
-  int32_t pad4, pad5;                      // whole 16-byte words (read with 16-byte loads)
+  int32_t pending;                         // STEP_FUSED: partial sums of an evaluation await their step
+  int32_t pad5;                            // whole 16-byte words (read with 16-byte loads)
 };
 static_assert(sizeof(SolverState) % 16 == 0, "SolverState is read in 16-byte words");
 

@@ -15,23 +15,26 @@
 
 namespace gpe {
 template <bool RR>
-static void launch(hipStream_t s, int nblocks, int threads, size_t smem, const ProbDev* probs, SolverState* st,
-                   const int2* bmap, const void* twd, const void* twf, hipEvent_t ev0, hipEvent_t ev1) {
+static void launch(hipStream_t s, int nblocks, int threads, size_t smem, const ProbDev* probs, SolverState* st_in,
+                   SolverState* st_out, const int2* bmap, const void* twd, const void* twf, int par, hipEvent_t ev0,
+                   hipEvent_t ev1) {
   if (ev0) {
     // events stamped by the dispatch itself (start and end of this kernel)
     hipExtLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0), RR>), dim3(nblocks), dim3(threads), smem, s,
-                          ev0, ev1, 0, probs, st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+                          ev0, ev1, 0, probs, st_in, st_out, bmap, (const cx<double>*)twd, (const cx<float>*)twf,
+                          par);
   } else {
     hipLaunchKernelGGL((k_solver_pass<GPE_ROLE, (GPE_PREC64 != 0), RR>), dim3(nblocks), dim3(threads), smem, s,
-                       probs, st, bmap, (const cx<double>*)twd, (const cx<float>*)twf);
+                       probs, st_in, st_out, bmap, (const cx<double>*)twd, (const cx<float>*)twf, par);
   }
 }
 void GPE_CAT(launch_solver_pass_r, GPE_ROLE, GPE_PREC64)(hipStream_t s, int nblocks, int threads, size_t smem,
-                                                         const ProbDev* probs, SolverState* st,
-                                                         const int2* bmap, const void* twd, const void* twf,
-                                                         hipEvent_t ev0, hipEvent_t ev1, int reread) {
+                                                         const ProbDev* probs, SolverState* st_in,
+                                                         SolverState* st_out, const int2* bmap, const void* twd,
+                                                         const void* twf, int par, hipEvent_t ev0, hipEvent_t ev1,
+                                                         int reread) {
   constexpr bool epi = GPE_ROLE == R_FINAL || GPE_ROLE == R_SOLO;
-  if (epi && reread) launch<epi>(s, nblocks, threads, smem, probs, st, bmap, twd, twf, ev0, ev1);
-  else launch<false>(s, nblocks, threads, smem, probs, st, bmap, twd, twf, ev0, ev1);
+  if (epi && reread) launch<epi>(s, nblocks, threads, smem, probs, st_in, st_out, bmap, twd, twf, par, ev0, ev1);
+  else launch<false>(s, nblocks, threads, smem, probs, st_in, st_out, bmap, twd, twf, par, ev0, ev1);
 }
 }  // namespace gpe

@@ -223,12 +223,15 @@ __global__ void __launch_bounds__(256) k_max_imag(const cx<double>* __restrict__
 }
 
 // ---- Cayley retraction (Theorem 3.3) on plain vectors ----
-__global__ void __launch_bounds__(256) k_retract_reduce(const cx<double>* __restrict__ x, const cx<double>* __restrict__ g,
+// T: element type of x, g, y (complex float64, or complex float32 with the
+// products converted to and summed in float64)
+template <typename T>
+__global__ void __launch_bounds__(256) k_retract_reduce(const cx<T>* __restrict__ x, const cx<T>* __restrict__ g,
                                                         int64_t m, double* __restrict__ part) {
   __shared__ double red[3 * 16];
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const cx<double> a = x[i], b = g[i];
+    const cx<double> a = cvt<double>(x[i]), b = cvt<double>(g[i]);
     acc[0] += redot(a, b);
     acc[1] += abs2(a);
     acc[2] += abs2(b);
@@ -241,8 +244,9 @@ __global__ void __launch_bounds__(256) k_retract_reduce(const cx<double>* __rest
   }
 }
 
-__global__ void __launch_bounds__(256) k_retract_apply(const cx<double>* __restrict__ x, const cx<double>* __restrict__ g,
-                                                       cx<double>* __restrict__ y, int64_t m, double tau,
+template <typename T>
+__global__ void __launch_bounds__(256) k_retract_apply(const cx<T>* __restrict__ x, const cx<T>* __restrict__ g,
+                                                       cx<T>* __restrict__ y, int64_t m, double tau,
                                                        const double* __restrict__ part, int np,
                                                        double* __restrict__ coeffs) {
   __shared__ double red[4];
@@ -253,7 +257,7 @@ __global__ void __launch_bounds__(256) k_retract_apply(const cx<double>* __restr
   const double p = ((1.0 + tau * a) * (1.0 + tau * a) - tau * tau * nx * ng) / den;
   const double q = -2.0 * tau * nx / den;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = p * x[i] + q * g[i];
+    y[i] = cvt<T>(p * cvt<double>(x[i]) + q * cvt<double>(g[i]));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     coeffs[0] = p; coeffs[1] = q; coeffs[2] = a; coeffs[3] = nx; coeffs[4] = ng;
   }
@@ -332,11 +336,17 @@ void launch_apply_finalize(hipStream_t s, const ProbDev* probs, const double* to
                            double* out) {
   hipLaunchKernelGGL(k_apply_finalize, dim3(1), dim3(kSumThreads), 0, s, probs, tot, rpart, nr, out);
 }
+template <typename T>
+static void retract_t(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
+                      double* part, double* coeffs) {
+  hipLaunchKernelGGL(k_retract_reduce<T>, dim3(nblk), dim3(256), 0, s, (const cx<T>*)x, (const cx<T>*)g, m, part);
+  hipLaunchKernelGGL(k_retract_apply<T>, dim3(nblk), dim3(256), 0, s, (const cx<T>*)x, (const cx<T>*)g, (cx<T>*)y, m,
+                     tau, part, nblk, coeffs);
+}
 void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void* y, int64_t m, double tau,
-                    double* part, double* coeffs) {
-  hipLaunchKernelGGL(k_retract_reduce, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, (const cx<double>*)g, m, part);
-  hipLaunchKernelGGL(k_retract_apply, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, (const cx<double>*)g,
-                     (cx<double>*)y, m, tau, part, nblk, coeffs);
+                    double* part, double* coeffs, int fp64) {
+  if (fp64) retract_t<double>(s, nblk, x, g, y, m, tau, part, coeffs);
+  else retract_t<float>(s, nblk, x, g, y, m, tau, part, coeffs);
 }
 void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* part) {
   hipLaunchKernelGGL(k_max_imag, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, m, part);

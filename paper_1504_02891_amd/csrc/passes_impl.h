@@ -556,6 +556,33 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, 
   }
 }
 
+// STEP_FUSED: the scalar step of the previous evaluation, run by every
+// workgroup of the first pass on its own copy of the state (each reduces the
+// same partial sums in the same order, so every copy gets the same bits);
+// the workgroup of tile 0 stores the new state for the later passes and the
+// host.  `part1_prev` holds the previous evaluation's first-pass partials.
+// Every thread of the workgroup must call it; S is updated in every thread.
+__device__ __forceinline__ void fused_step(const ProbDev& P, SolverState& S, const double* part1_prev,
+                                           SolverState* out, bool writer, int prec64, double* red) {
+  __shared__ SolverState sh;
+  if (S.pending && S.mode != M_IDLE) {
+    double r1[S1_COUNT], rf[SF_COUNT];
+    step_reductions(part1_prev, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red);
+    if (threadIdx.x == 0) {
+      SolverState L = S;
+      step_logic(P, L, r1, rf, prec64);
+      L.pending = L.mode != M_IDLE ? 1 : 0;
+      sh = L;
+      if (writer) *out = L;
+    }
+    __syncthreads();
+    S = sh;
+  } else {
+    S.pending = S.mode != M_IDLE ? 1 : 0;
+    if (writer && threadIdx.x == 0) *out = S;
+  }
+}
+
 // The state fields the passes read.
 #define GPE_PASS_STATE_FIELDS(F) \
   F(S.mode); F(S.cur); F(S.src); F(S.force_norm); F(S.p); F(S.q); F(S.pm1); F(S.n_b); F(S.a_b); \
@@ -576,7 +603,7 @@ __device__ __forceinline__ void pin_desc_fields(ProbDev& P) {
   pin_reg(P.v_arr); pin_reg(P.v_axis);
   pin_reg(P.xf[0]); pin_reg(P.xf[1]); pin_reg(P.gf[0]); pin_reg(P.gf[1]);
   pin_reg(P.s[0]); pin_reg(P.s[1]); pin_reg(P.d[0]); pin_reg(P.d[1]);
-  pin_reg(P.xk); pin_reg(P.gk); pin_reg(P.t); pin_reg(P.part1); pin_reg(P.partF);
+  pin_reg(P.xk); pin_reg(P.gk); pin_reg(P.t); pin_reg(P.part1); pin_reg(P.part1x); pin_reg(P.partF);
 }
 
 // Dispatch on the problem's mode.  PREC64: every array float64.
@@ -599,13 +626,18 @@ __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverSt
 }
 
 // `bmap` maps a workgroup to (problem, tile); null for a single problem
-// (workgroup b is tile b of problem 0).  RR: see solver_tile.
+// (workgroup b is tile b of problem 0).  RR: see solver_tile.  The passes
+// read the state from st_in; with STEP_FUSED the first pass stores the state
+// after its step in st_out (the host alternates two state arrays and passes
+// the evaluation's parity `par`, which also selects the first-pass partials
+// buffer); otherwise st_out is st_in and par is 0.
 template <int ROLE, bool PREC64, bool RR>
 __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__ probs,
-                                                     SolverState* __restrict__ states,
+                                                     SolverState* __restrict__ st_in,
+                                                     SolverState* __restrict__ st_out,
                                                      const int2* __restrict__ bmap,
                                                      const cx<double>* __restrict__ twd,
-                                                     const cx<float>* __restrict__ twf) {
+                                                     const cx<float>* __restrict__ twf, int par) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[SF_COUNT * 16];
   const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -614,8 +646,17 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   // scalar registers
   ProbDev P = probs[bm.x];
   pin_desc_fields(P);
-  SolverState S = states[bm.x];
+  SolverState S = st_in[bm.x];
   GPE_PASS_STATE_FIELDS(pin_reg);
+  double* const part1_other = par ? P.part1 : P.part1x;
+  if (par) P.part1 = P.part1x;
+  if constexpr (ROLE == R_FIRST) {
+    if (P.step_at == STEP_FUSED) {
+      fused_step(P, S, part1_other, st_out + bm.x, bm.y == 0, PREC64 ? 1 : 0, red);
+      GPE_PASS_STATE_FIELDS(make_uniform);
+      GPE_PASS_STATE_FIELDS(pin_reg);
+    }
+  }
   if (S.mode == M_IDLE) return;
   const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   switch (n) {
@@ -630,7 +671,7 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   }
   if constexpr (ROLE == R_FINAL || ROLE == R_SOLO)
     if (P.step_at == STEP_LAST_GROUP)
-      step_if_last(P, states + bm.x, ROLE == R_SOLO ? 1 : pick3(P.tiles, P.dim - 1), PREC64 ? 1 : 0, red);
+      step_if_last(P, st_in + bm.x, ROLE == R_SOLO ? 1 : pick3(P.tiles, P.dim - 1), PREC64 ? 1 : 0, red);
 }
 
 }  // namespace gpe

@@ -72,6 +72,21 @@ def test_host_only_entry_points():
     assert L.gpe_apply_h(None, None, 0, None, None, None) == nat.GPE_EINVAL
     assert L.gpe_solve(None, None, None, None, None) == nat.GPE_EINVAL
     assert L.gpe_set_plan(None, None, 0, None, 0) == nat.GPE_EINVAL
+    assert L.gpe_hess_vec(None, None, 0, None, None, 0.0, None) == nat.GPE_EINVAL
+    assert L.gpe_retract(None, 1, 0, None, None, 0.1, None, None) == nat.GPE_EINVAL
+
+
+def test_binding_argument_counts_match_the_header():
+    # each ctypes prototype has as many parameters as the header declares
+    nat = _lib()
+    L = nat.lib()
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    decls = re.findall(r"^\s*(?:int|void|const char\*)\s+(gpe_\w+)\s*\(([^)]*)\)", txt, re.M)
+    assert len(decls) == len(nat.EXPORTS)
+    for name, params in decls:
+        params = params.strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        assert len(getattr(L, name).argtypes) == n, name
 
 
 def test_oracle_and_library_defaults_agree():

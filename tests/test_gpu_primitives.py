@@ -85,6 +85,7 @@ def test_apply_h_matches_oracle(dev, p, prec):
     ref = disc.h_full(p, phi_in)
     tol = _bound(p, phi_in, prec)
     err = float(np.max(np.abs(got - ref)))
+    print(f"apply_h {prec} {_cid(p)}: error/bound = {err / tol:.3f}")
     assert err <= tol, (err, tol)
     up = UnifiedProblem(p)
     o = up.outputs(up.to_x(phi_in))
@@ -155,6 +156,44 @@ def test_hess_vec_matches_oracle(dev, p):
     scale = 2 * _bound(p, s / math.sqrt(up.hvol), "fp64") * math.sqrt(up.hvol) \
         + 1e-13 * float(np.max(np.abs(ref)))
     assert float(np.max(np.abs(got - ref))) <= scale
+
+
+@pytest.mark.parametrize("p", [CASES[1], CASES[3], CASES[5], CASES[6]], ids=_cid)
+def test_hess_vec_fp32_matches_oracle(dev, p):
+    # mixed precision: s in complex64, transforms in float32, X_k complex128,
+    # the pointwise terms in float64 rounded to float32 once on store
+    up = UnifiedProblem(p)
+    xk = up.to_x(_field(p, 5))
+    s32 = (1e-2 * up.to_x(_field(p, 6))).astype(np.complex64)
+    s = s32.astype(np.complex128)           # the value the kernel saw
+    delta = 0.37
+    ref = up.hess(xk, s) + delta * s
+    got = dev.hess_vec(p, torch.from_numpy(xk).cuda(), torch.from_numpy(s32).cuda(), delta,
+                       precision="mixed").cpu().numpy().astype(np.complex128)
+    bound = 2 * _bound(p, s / math.sqrt(up.hvol), "mixed") * math.sqrt(up.hvol) \
+        + 2.0 ** -24 * float(np.max(np.abs(ref)))
+    err = float(np.max(np.abs(got - ref)))
+    print(f"hess_vec fp32 {_cid(p)}: error/bound = {err / bound:.3f}")
+    assert err <= bound, (err, bound)
+
+
+@pytest.mark.parametrize("m", [1, 255, 65536 + 17])
+def test_retract_fp32_matches_cayley_closed_form(dev, m):
+    # complex64 data, float64 reductions and coefficients
+    rng = np.random.default_rng(m + 1)
+    x = (rng.standard_normal(m) + 1j * rng.standard_normal(m)).astype(np.complex64)
+    x /= np.float32(np.linalg.norm(x))
+    g = (7.0 * (rng.standard_normal(m) + 1j * rng.standard_normal(m))).astype(np.complex64)
+    tau = 0.013
+    y, co = dev.retract(torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda(), tau, precision="mixed")
+    x64, g64 = x.astype(np.complex128), g.astype(np.complex128)
+    a, nx, ng = re_dot(x64, g64), re_dot(x64, x64), re_dot(g64, g64)
+    p, q = cayley_coefficients(tau, a, nx, ng)
+    assert abs(co["p"] - p) < 1e-12 and abs(co["q"] - q) < 1e-12
+    assert abs(co["nx"] - nx) < 1e-12 * nx and abs(co["ng"] - ng) < 1e-12 * ng
+    yr = p * x64 + q * g64
+    assert y.dtype == torch.complex64
+    assert float(np.max(np.abs(y.cpu().numpy().astype(np.complex128) - yr))) <= 2.0 ** -24 * float(np.max(np.abs(yr)))
 
 
 @pytest.mark.parametrize("m", [1, 255, 65536 + 17])
