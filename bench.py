@@ -7,11 +7,14 @@ workload's problem(s) from the same initial data, with inputs resident in
 HBM.  Default workload: the 2D rotating condensate (256x256 Fourier grid on
 [-12,12]^2, beta = 1000, Omega = 0.9), mixed precision, residual 1e-6.
 
-Prints one JSON line.  Extra fields: the roofline of the dominant kernel
-(the last-axis pass, timed with HIP events stamped by the dispatch of every
-k-th launch during the timed steps), the same solve on the plain
-float64 path, the H(phi)phi bandwidth of gpe_apply_h on a 256^3 grid, and
-the float64 CPU oracle timed on a bounded sample.
+Prints one JSON line.  The timed steps run the library's default path
+(chunks of evaluations replayed as hipGraphs).  Extra fields: the roofline
+of the dominant kernel (the last-axis pass, timed with HIP events stamped by
+the dispatch of every k-th launch of one more, untimed, solve with plain
+launches), the same solve on the plain float64 path, the batched sweep of 64
+rotating problems in both precisions, the H(phi)phi bandwidth of gpe_apply_h
+on a 512x512x256 grid (working set above 1 GB) and on 256^3, and the float64
+CPU oracle timed on a bounded sample on one core and on every core.
 """
 from __future__ import annotations
 
@@ -27,8 +30,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Bytes the last-axis (final) pass must move per grid point in each mode:
-# every input array read once, every output written once.
+# Algorithmic bytes of the last-axis pass per grid point, the canonical fused
+# pass set of the method's evaluation: the last pass reads the point and the
+# accumulated transforms of the other axes and writes the gradient, 3 b for
+# element size b (8 complex64, 16 complex128).
+CANON_LAST_PASS = 3
+
+# The solver's own model of the same pass, per mode (every array it reads or
+# writes once: the fused retraction, Newton model and reductions add arrays):
 #   F-mode  : X_b, G_b, t read; Y, G_Y written                      -> 5 arrays of the iterate type
 #   W-mode  : X_k, G_k (float64) + S_b, D_b, t read; S', D' written -> 2*16 + 5*b
 #   outer   : X_k or X_f, S (src), t read; X_k, G_k written; S, D zeroed
@@ -63,41 +72,82 @@ CASCADE = [16, 4]           # cascade2d: problems, levels (64^2 .. 512^2); --cas
 CASCADE_LEVEL_TOL = 1e-4    # residual at which a coarse level hands over to the next
 
 
-def cpu_baseline(probs, phi0s, gpu_nfe, budget_s, opts):
-    """Time the float64 oracle's Algorithm 2 on the first problem for about
-    `budget_s` seconds of one core, then scale to solves/s with the
-    evaluation count the GPU solve needed."""
-    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+def _oracle_sample(args):
+    """One bounded run of the oracle's Algorithm 2 (single-threaded numpy):
+    the K_init steps of Algorithm 1, then Newton steps, stopped after about
+    n_eval evaluations (each Newton step runs at most K_sub + 1)."""
+    p, phi0, tol, n_eval = args
+    for v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
     import numpy as np
     from oracle import newton
+    from oracle.unified import UnifiedProblem
+    up = UnifiedProblem(p)
+    x0 = up.to_x(np.asarray(phi0, dtype=np.complex128))
+    o = newton.Options(tol=tol)
+    o.max_outer = max(1, (n_eval - o.k_init) // (o.k_sub + 1))
+    t = time.perf_counter()
+    res = newton.regularized_newton(up, x0, o)
+    return time.perf_counter() - t, res.nfe
+
+
+def _cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:      # lscpu missing: the model stays unnamed
+        pass
+    return None
+
+
+def cpu_baseline(probs, phi0s, gpu_nfe, budget_s, opts):
+    """The float64 oracle's Algorithm 2 on the first problem on the host:
+    one process on one core for about `budget_s` seconds, then one such
+    process per core at once (independent solves, the way a host would run a
+    batch of problems); each leg's seconds per evaluation are scaled to
+    solves/s by the evaluation count the GPU solve needed."""
+    import multiprocessing as mp
+    import numpy as np
     from oracle.unified import UnifiedProblem
     p, phi0 = probs[0], phi0s[0]
     up = UnifiedProblem(p)
     x0 = up.to_x(np.asarray(phi0, dtype=np.complex128))
-    o = newton.Options(tol=opts["tol"])
     # probe the cost of one evaluation (after a warm-up call), then size the
-    # sample to the budget
+    # samples to the budget
     up.f_and_grad(x0)
     t = time.perf_counter()
     for _ in range(5):
         up.f_and_grad(x0)
     per = (time.perf_counter() - t) / 5
     n_eval = max(300, int(budget_s / max(per, 1e-6)))
-    # K_init steps, then Newton steps; their inner loops stop early on this
-    # workload (about 50 evaluations per Newton step, at most K_sub = 200)
-    o.max_outer = max(1, (n_eval - o.k_init) // 60)
+    dt1, nfe1 = _oracle_sample((p, phi0, opts["tol"], n_eval))
+    spe1 = dt1 / max(nfe1, 1)
+    ncpu = os.cpu_count() or 1
+    # one GPU's job gets a share of 16 host cores on the GPU box
+    cores = max(1, min(ncpu, 16))
     t = time.perf_counter()
-    res = newton.regularized_newton(up, x0, o)
-    dt = time.perf_counter() - t
-    sec_per_eval = dt / max(res.nfe, 1)
-    value = 1.0 / (sec_per_eval * gpu_nfe)
-    return {"value": value, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {res.nfe} float64 evaluations of Algorithm 2 on problem 0 "
-                       f"({dt:.1f} s, {1e3 * sec_per_eval:.3f} ms/evaluation, 1 thread), scaled "
-                       f"by the {gpu_nfe} evaluations of the GPU solve")}
+    with mp.get_context("spawn").Pool(cores) as pool:
+        runs = pool.map(_oracle_sample, [(p, phi0, opts["tol"], n_eval)] * cores)
+    wall = time.perf_counter() - t
+    evals = sum(n for _, n in runs)
+    spe_all = wall / max(evals, 1)          # aggregate seconds per evaluation over all processes
+    value1 = 1.0 / (spe1 * gpu_nfe)
+    return {"value": value1, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "cpu_model": _cpu_model(), "cpu_count": ncpu,
+            "sample": (f"first {nfe1} float64 evaluations of Algorithm 2 on problem 0 "
+                       f"({dt1:.1f} s, {1e3 * spe1:.3f} ms/evaluation, 1 thread), scaled "
+                       f"by the {gpu_nfe} evaluations of the GPU solve"),
+            "all_cores": {"value": 1.0 / (spe_all * gpu_nfe), "unit": "solves/s", "cores": cores,
+                          "sample": (f"{cores} processes at once, each the same bounded run "
+                                     f"({evals} evaluations in {wall:.1f} s of wall time, "
+                                     f"{1e3 * spe_all:.3f} ms per evaluation aggregate)")}}
 
 
 PLANS_FILE = os.path.join(ROOT, "profiles", "launch_plans_mi355x.json")
+HPHI_BIG = (512, 512, 256)    # H(phi)phi grid with a working set above 1 GB in both precisions
 
 
 def recorded_traffic(workload_name, ev32, ev64):
@@ -126,8 +176,8 @@ def recorded_traffic(workload_name, ev32, ev64):
     return round(tot / (ev32 + ev64))
 
 
-def hphi_bandwidth(n=256, reps=20):
-    """H(phi)phi throughput through gpe_apply_h on an n^3 grid (the 3D lattice
+def hphi_bandwidth(dims=(256, 256, 256), reps=20):
+    """H(phi)phi throughput through gpe_apply_h on a 3D grid (the 3D lattice
     problem's potential and beta), float32 and float64.  Bytes per
     application: the canonical fused pass set (x pass: read phi, write t;
     y pass: read phi and t, write t; z pass: read phi and t, write H phi) plus
@@ -135,12 +185,13 @@ def hphi_bandwidth(n=256, reps=20):
     import torch
     import workloads as W
     from paper_1504_02891_amd import api
-    p = W.Problem(dim=3, n=(n, n, n), lo=(-16.0,) * 3, hi=(16.0,) * 3, beta=1600.0, lattice_amp=100.0)
-    m = n ** 3
-    out = {"grid": f"{n}^3", "bytes_per_point": "10 b (b = 8 complex64, 16 complex128)"}
+    p = W.Problem(dim=3, n=dims, lo=(-16.0,) * 3, hi=(16.0,) * 3, beta=1600.0, lattice_amp=100.0)
+    m = dims[0] * dims[1] * dims[2]
+    n = dims
+    out = {"grid": "x".join(map(str, dims)), "bytes_per_point": "10 b (b = 8 complex64, 16 complex128)"}
     for prec, dt, b in (("mixed", torch.complex64, 8), ("fp64", torch.complex128, 16)):
         gen = torch.Generator(device="cuda").manual_seed(7)
-        x = (torch.randn(n, n, n, dtype=torch.float64, device="cuda", generator=gen) + 0j).to(dt)
+        x = (torch.randn(n[2], n[1], n[0], dtype=torch.float64, device="cuda", generator=gen) + 0j).to(dt)
         hx = torch.empty_like(x)
         api.apply_h(p, x, precision=prec, out=hx)          # warm-up (workspace, code objects)
         torch.cuda.synchronize()
@@ -159,7 +210,106 @@ def hphi_bandwidth(n=256, reps=20):
         out[prec] = {"us_per_apply": round(1e6 * dt_s, 1), "gbs": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "us_with_readback": round(1e6 * lat, 1),
                      "working_set_mb": round(3 * b * m / 2 ** 20)}
+        torch.cuda.synchronize()
         del x, hx
+    return out
+
+
+def install_plans(api, probs, precs, levels, retune):
+    """Launch plans (untimed): the plans gpe_autotune picked for these grids on
+    MI355X, recorded in PLANS_FILE, so that every run tiles the grids alike
+    and follows the same trajectory (the autotuner's choice between plans
+    within a few per cent of each other changes with timing noise, and the
+    tiling sets the order of the reductions); grids without a recorded plan,
+    or all with `retune`, are tuned here.  A mixed solve's FP64 continuation
+    and the fp64 comparison solve take the FP64 plans."""
+    recorded = {}
+    if not retune and os.path.exists(PLANS_FILE):
+        recorded = json.load(open(PLANS_FILE))["plans"]
+    plans = {}
+    for p0 in probs:
+        for lvl in range(levels):      # every level's grid
+            p = p0.with_n([n << lvl for n in p0.n]) if lvl else p0
+            for prec in precs:
+                key = (prec, tuple(p.n[: p.dim]), getattr(p, "bc", "fourier"))
+                if key in plans:
+                    continue
+                rec = recorded.get(f"{prec} {'x'.join(map(str, key[1]))} {key[2]}")
+                if rec is not None:
+                    api.set_plan(p, prec, rec["threads"], rec["step_at"])
+                    plans[key] = dict(rec, source="recorded")
+                else:
+                    plans[key] = dict(api.autotune(p, prec), source="tuned")
+    return {f"{k[0]} {'x'.join(map(str, k[1]))} {k[2]}": v for k, v in plans.items()}
+
+
+def roofline(a, probs, results, cascade):
+    """Roofline of the final pass from one profiled solve: algorithmic bytes
+    per launch divided by the event-timed average launch duration (every k-th
+    launch sampled).  The algorithmic bytes are the canonical last pass's,
+    3 b per point with b the element size of the instance that ran (a mixed
+    solve's evaluations after the FP64 handover run the FP64 instance); the
+    solver's own per-mode byte model of the pass is given beside it."""
+    import numpy as np
+    mb, m64 = FINAL_BYTES["mixed"], FINAL_BYTES["fp64"]
+    pts = [int(np.prod(p.n[: p.dim])) for p in probs]
+    byt = canon = 0.0
+    nlaunch = launches = 0
+    ms = 0.0
+    ev32 = ev64 = 0
+    for rs in results:
+        for r, m in zip(rs, pts):
+            for k, key in enumerate(("nfe_f", "nfe_w", "nfe_outer")):
+                mode = key[4]
+                n32 = r["nfe_mixed"][k]
+                byt += m * (n32 * mb[mode] + (r[key] - n32) * m64[mode])
+                canon += m * CANON_LAST_PASS * (8 * n32 + 16 * (r[key] - n32))
+                ev32 += n32
+                ev64 += r[key] - n32
+        nlaunch += max(r["nfe"] for r in rs)
+        launches += rs[0]["pass_launches"]
+        ms += rs[0]["pass_ms"]
+    avg_ms = ms / max(launches, 1)
+    bpl, cpl = byt / max(nlaunch, 1), canon / max(nlaunch, 1)
+    ok = launches > 0 and not cascade
+    # (cascade: the result counters add the evaluations of four grid sizes,
+    # so no per-launch byte count; the single-grid workloads carry the line)
+    ach = cpl / (avg_ms * 1e-3) / 1e9 if ok else None
+    mach = bpl / (avg_ms * 1e-3) / 1e9 if ok else None
+    return {"bound": "hbm", "achieved": None if ach is None else round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(a.workload, ev32, ev64),
+            "kernel": "k_solver_pass<R_FINAL>", "evaluations": {"fp32_instance": ev32, "fp64_instance": ev64},
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+            "timing": (f"dispatch-stamped HIP events on every {a.profile_every}th launch of one profiled solve "
+                       "(plain launches) after the timed steps"),
+            "timed_launches": launches, "launches": nlaunch,
+            "bytes_per_launch": None if not ok else round(cpl),
+            "bytes_model": "canonical last pass: read the point and the other axes' transforms, write the "
+                           "gradient, 3 b per point",
+            "solver_model_bytes_per_launch": None if not ok else round(bpl),
+            "solver_model_frac": None if mach is None else round(mach / HBM_PEAK_GBS, 4)}
+
+
+def batch_leg(api, torch, np, opts):
+    """The batched sweep (64 rotating problems on 64^2/128^2/256^2, one launch
+    sequence for all): one solve in each precision."""
+    import workloads as W
+    probs, phi0s = W.rotating_sweep_2d()
+    phis = [torch.from_numpy(np.asarray(f, dtype=np.complex128)).cuda() for f in phi0s]
+    install_plans(api, probs, ("mixed", "fp64"), 1, False)
+    out = {"workload": "64 rotating 2D problems, 64^2/128^2/256^2 on [-12,12]^2, beta U[100,2000], "
+                       "Omega U[0,0.95], one batch"}
+    for prec in ("mixed", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rs = api.solve_batched(probs, phis, **dict(opts, precision=prec))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"value": round(len(probs) / dt, 4), "unit": "solves/s", "seconds": round(dt, 2),
+                     "converged": sum(r["status"] == 0 for r in rs), "max_nfe": max(r["nfe"] for r in rs),
+                     "fp32_evaluations": int(sum(sum(r["nfe_mixed"]) for r in rs)),
+                     "evaluations": int(sum(r["nfe"] for r in rs))}
     return out
 
 
@@ -179,9 +329,9 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20000,
                     help="Newton-step cap per solve (lower it only for short profiler runs)")
     ap.add_argument("--profile-every", type=int, default=61,
-                    help="time every k-th launch of the final pass with HIP events (coprime with the "
-                         "64-evaluation chunk, so the samples cover every position in a chunk: the first "
-                         "evaluations after a host check run slower)")
+                    help="in the profiled solve, time every k-th launch of the final pass with HIP events "
+                         "(coprime with the 64-evaluation chunk, so the samples cover every position in a "
+                         "chunk: the first evaluations after a host check run slower); 0: no profiled solve")
     ap.add_argument("--no-autotune", action="store_true",
                     help="no launch plans: the library's built-in workgroup sizes and step placement")
     ap.add_argument("--retune", action="store_true",
@@ -192,8 +342,9 @@ def main():
                          "whole solve stays mixed)")
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="timed solves of the same workload on the plain float64 path (0: skip)")
-    ap.add_argument("--no-hphi", action="store_true", help="skip the 256^3 H(phi)phi bandwidth measurement")
-    ap.add_argument("--only-hphi", action="store_true", help="only the 256^3 H(phi)phi bandwidth measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep (both precisions)")
+    ap.add_argument("--no-hphi", action="store_true", help="skip the H(phi)phi bandwidth measurement")
+    ap.add_argument("--only-hphi", action="store_true", help="only the H(phi)phi bandwidth measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 10 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -208,7 +359,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 10}))
         return
     if a.only_hphi:
-        print(json.dumps({"hphi": hphi_bandwidth()}), flush=True)
+        print(json.dumps({"hphi": hphi_bandwidth(HPHI_BIG), "hphi_256": hphi_bandwidth()}), flush=True)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU (independent problems shard without "
@@ -231,10 +382,11 @@ def main():
     if a.switch_resid is not None:
         opts["switch_resid"] = a.switch_resid
 
-    # timed steps: plain launches with every k-th last-axis pass timed by
-    # events stamped by its own dispatch (graph replay would need event
-    # nodes, which add their packets' time to the interval)
-    def step(profile):
+    # one step: a full solve of the workload; profile > 0 gives the profiled
+    # variant (plain launches, every k-th final pass timed by events stamped
+    # by its own dispatch; graph replay would need event nodes, which add
+    # their packets' time to the interval)
+    def step(profile=0):
         kw = dict(opts, profile=profile, use_graph=0 if profile else 1)
         if cascade:
             outs, rs = api.solve_cascadic(probs, phis, CASCADE[1], level_tol=CASCADE_LEVEL_TOL, **kw)
@@ -245,83 +397,30 @@ def main():
         outs, rs = api.solve_batched(probs, phis, **kw)
         return rs
 
-    # launch plans (untimed): the plans gpe_autotune picked for these grids on
-    # MI355X, recorded in PLANS_FILE, so that every run tiles the grids alike
-    # and follows the same trajectory (the autotuner's choice between plans
-    # within a few per cent of each other changes with timing noise, and the
-    # tiling sets the order of the reductions); grids without a recorded plan,
-    # or all with --retune, are tuned here.  A mixed solve's FP64 continuation
-    # and the fp64 comparison solve take the FP64 plans.
-    recorded = {}
-    if not a.retune and os.path.exists(PLANS_FILE):
-        recorded = json.load(open(PLANS_FILE))["plans"]
     plans = {}
     if not a.no_autotune:
-        for p0 in probs:
-            for lvl in range(CASCADE[1] if cascade else 1):      # every level's grid
-                p = p0.with_n([n << lvl for n in p0.n]) if lvl else p0
-                for prec in (("mixed", "fp64") if a.precision == "mixed" else ("fp64",)):
-                    key = (prec, tuple(p.n[: p.dim]), getattr(p, "bc", "fourier"))
-                    if key in plans:
-                        continue
-                    rec = recorded.get(f"{prec} {'x'.join(map(str, key[1]))} {key[2]}")
-                    if rec is not None:
-                        api.set_plan(p, prec, rec["threads"], rec["step_at"])
-                        plans[key] = dict(rec, source="recorded")
-                    else:
-                        plans[key] = dict(api.autotune(p, prec), source="tuned")
+        plans = install_plans(api, probs, ("mixed", "fp64") if a.precision == "mixed" else ("fp64",),
+                              CASCADE[1] if cascade else 1, a.retune)
     for _ in range(a.warmup):
-        step(a.profile_every)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
     for _ in range(a.steps):
-        results.append(step(profile=a.profile_every))
+        results.append(step())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nsolves = a.steps * len(probs)
     value = nsolves / dt
     last = results[-1]
     conv = all(r["status"] == 0 for rs in results for r in rs)
-
-    # roofline of the final pass over every timed step: algorithmic bytes per
-    # launch (all problems' evaluations in that launch, by mode) divided by the
-    # event-timed average launch duration (every k-th launch sampled)
-    # (a mixed solve's evaluations after the FP64 handover run the FP64
-    # instance of the pass: each is priced by the byte model of its precision)
-    mb, m64 = FINAL_BYTES["mixed"], FINAL_BYTES["fp64"]
+    same = all(r["nfe"] == l["nfe"] for rs in results for r, l in zip(rs, last))
     pts = [int(np.prod(p.n[: p.dim])) for p in probs]
-    byt, nlaunch = 0.0, 0
-    launches, ms = 0, 0.0
-    ev32 = ev64 = 0
-    for rs in results:
-        for r, m in zip(rs, pts):
-            for k, key in enumerate(("nfe_f", "nfe_w", "nfe_outer")):
-                mode = key[4]
-                n32 = r["nfe_mixed"][k]
-                byt += m * (n32 * mb[mode] + (r[key] - n32) * m64[mode])
-                ev32 += n32
-                ev64 += r[key] - n32
-        nlaunch += max(r["nfe"] for r in rs)
-        launches += rs[0]["pass_launches"]
-        ms += rs[0]["pass_ms"]
-    avg_ms = ms / max(launches, 1)
-    bpl = byt / max(nlaunch, 1)
-    achieved = bpl / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    if cascade:
-        # the result counters add the evaluations of all four grid sizes: no
-        # per-launch byte count (the single-grid workloads carry the roofline)
-        achieved, bpl = None, None
-    roof = {"bound": "hbm", "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": recorded_traffic(a.workload, ev32, ev64),
-            "kernel": "k_solver_pass<R_FINAL>", "evaluations": {"fp32_instance": ev32, "fp64_instance": ev64},
-            "avg_launch_us": round(avg_ms * 1e3, 3),
-            "timing": f"dispatch-stamped HIP events on every {a.profile_every}th launch of the timed steps",
-            "timed_launches": launches, "launches": nlaunch,
-            "bytes_per_launch": None if bpl is None else round(bpl)}
+    roof = None
+    if a.profile_every > 0:
+        roof = roofline(a, probs, [step(a.profile_every)], cascade)
 
+    ev = sum(sum(r["nfe_mixed"]) for r in last)
     out = {
         "metric": "ground-state solves/sec + H\u00b7\u03c6 HBM GB/s; mixed vs FP64 GPU at resid 1e-6",
         "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
@@ -333,11 +432,13 @@ def main():
         "config": {"workload": desc, "precision": a.precision, "tol": a.tol, "problems": len(probs),
                    "grid_points": pts},
         "converged": conv,
+        "same_trajectory_every_step": same,
         "nfe_per_solve": [r["nfe"] for r in last],
+        "fp32_share_of_evaluations": round(ev / max(1, sum(r["nfe"] for r in last)), 4),
         "energy": [r["energy"] for r in last][:4],
         "resid": [r["resid"] for r in last][:4],
         "roofline": roof,
-        "launch_plans": {f"{k[0]} {'x'.join(map(str, k[1]))} {k[2]}": v for k, v in plans.items()},
+        "launch_plans": plans,
     }
     if cascade:
         out["config"]["grid_points"] = [int(np.prod(p.n[: p.dim])) << (2 * (CASCADE[1] - 1)) for p in probs]
@@ -359,8 +460,11 @@ def main():
                        "converged": all(r["status"] == 0 for rs in r64 for r in rs),
                        "nfe_per_solve": [r["nfe"] for r in r64[-1]],
                        "energy": [r["energy"] for r in r64[-1]][:4], "resid": [r["resid"] for r in r64[-1]][:4]}
+    if a.workload == "rot2d" and not a.no_batch:
+        out["batch2d"] = batch_leg(api, torch, np, dict(tol=a.tol, max_outer=a.max_outer))
     if not a.no_hphi:
-        out["hphi"] = hphi_bandwidth()
+        out["hphi"] = hphi_bandwidth(HPHI_BIG)
+        out["hphi_256"] = hphi_bandwidth()
     if not a.no_cpu_baseline and not cascade:      # the oracle's sample is one grid's Algorithm 2
         out["cpu_baseline"] = cpu_baseline(probs, phi0s, last[0]["nfe"], a.cpu_budget, opts)
     print(json.dumps(out), flush=True)

@@ -53,3 +53,25 @@ def test_recorded_traffic_weights_the_instances(tmp_path, monkeypatch):
     assert bench.recorded_traffic("lattice3d", 100, 300) is None
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.recorded_traffic("rot2d", 100, 300) is None
+
+
+def test_roofline_prices_the_canonical_last_pass():
+    # achieved = 3 b M per launch (b by the instance that ran) / mean event
+    # time; the solver's own per-mode model is reported beside it
+    sys.path.insert(0, ROOT)
+    import argparse
+    import bench
+    import workloads as W
+    p, _ = W.rotating_2d()
+    r = {"nfe": 1000, "nfe_f": 100, "nfe_w": 880, "nfe_outer": 20, "nfe_mixed": [100, 300, 0],
+         "pass_launches": 50, "pass_ms": 50 * 0.010}
+    a = argparse.Namespace(workload="harm1d", profile_every=61)
+    roof = bench.roofline(a, [p], [[r]], cascade=False)
+    m = 256 * 256
+    canon = m * 3 * (8 * 400 + 16 * 600) / 1000
+    assert roof["bytes_per_launch"] == round(canon)
+    assert abs(roof["achieved"] - round(canon / 10e-6 / 1e9, 1)) < 1e-9
+    assert abs(roof["frac"] - round(roof["achieved"] / 8000.0, 4)) < 1e-4
+    model = m * (100 * 40 + 300 * 72 + 580 * 112 + 20 * 112) / 1000
+    assert roof["solver_model_bytes_per_launch"] == round(model)
+    assert bench.roofline(a, [p], [[r]], cascade=True)["achieved"] is None
