@@ -217,6 +217,29 @@ int gpe_apply_h(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision,
                 const void* phi, void* h_phi, double* scalars);
 
 /*
+ * gpe_apply_h for callers that cannot allocate device memory: code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same H(phi)phi and scalars as gpe_apply_h (the same kernels), with every
+ * intermediate (descriptor, potential tables, partial sums, the passes'
+ * accumulator) in one fixed scratch array per GPU that the library sets up
+ * in gpe_ctx_create and holds until the process ends (about 35 MB); the
+ * call allocates nothing and never waits on the host.
+ *   Limit: at most 2^21 grid points; larger grids return GPE_EUNSUPPORTED
+ *   (gpe_last_error says why) before any device work.
+ *   phi, h_phi: DEVICE arrays as for gpe_apply_h (complex128, or complex64
+ *   with GPE_PREC_MIXED).
+ *   scalars_dev: DEVICE double[10] out (the scalars of gpe_apply_h, same
+ *   order), or NULL.
+ *   The trap and lattice tables are evaluated on the device (the same
+ *   formula as gpe_apply_h's host tables, so V may differ in its last bit).
+ *   Every call on a GPU reuses that GPU's scratch: calls that overlap on one
+ *   GPU (two contexts, two host threads, two streams) race; calls ordered on
+ *   one stream do not.  Nothing in the scratch needs clearing between calls.
+ */
+int gpe_apply_h_noalloc(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision,
+                        const void* phi, void* h_phi, double* scalars_dev);
+
+/*
  * Hessian-vector product of the regularized Newton model (Lemma 3.1, §3.2),
  * in X units:  out = A s + 4 alpha (|x_k|^2 s + 2 Re(conj(x_k) s) x_k) + delta s.
  *   precision  GPE_PREC_FP64: s and out complex128, transforms in float64;

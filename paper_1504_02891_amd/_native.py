@@ -34,7 +34,7 @@ GPE_STOP_CRIT1 = 1
 GPE_STOP_CRIT2 = 2
 
 EXPORTS = ("gpe_ctx_create", "gpe_ctx_destroy", "gpe_options_default", "gpe_strerror",
-           "gpe_last_error", "gpe_apply_h", "gpe_hess_vec", "gpe_retract", "gpe_solve",
+           "gpe_last_error", "gpe_apply_h", "gpe_apply_h_noalloc", "gpe_hess_vec", "gpe_retract", "gpe_solve",
            "gpe_solve_batched", "gpe_prolong", "gpe_solve_cascadic", "gpe_autotune", "gpe_set_plan")
 
 
@@ -101,6 +101,7 @@ def lib():
     L.gpe_last_error.argtypes = []
     L.gpe_last_error.restype = C.c_char_p
     L.gpe_apply_h.argtypes = [vp, C.POINTER(Problem), i32, vp, vp, C.POINTER(dbl)]
+    L.gpe_apply_h_noalloc.argtypes = [vp, C.POINTER(Problem), i32, vp, vp, vp]
     L.gpe_hess_vec.argtypes = [vp, C.POINTER(Problem), i32, vp, vp, dbl, vp]
     L.gpe_retract.argtypes = [vp, C.c_int64, i32, vp, vp, dbl, vp, C.POINTER(dbl)]
     L.gpe_solve.argtypes = [vp, C.POINTER(Problem), C.POINTER(Options), vp, C.POINTER(Result)]

@@ -140,6 +140,28 @@ def apply_h(p, phi, precision="fp64", v=None, scalars=True, out=None):
     return out, (dict(zip(SCALAR_NAMES, list(sc))) if scalars else None)
 
 
+def apply_h_noalloc(p, phi, precision="fp64", v=None, out=None, scalars_out=None):
+    """gpe_apply_h_noalloc: H(phi) phi through the library's fixed scratch
+    (no device allocation in the call); ``scalars_out``: optional float64
+    CUDA tensor of 10 elements receiving the scalars on the device."""
+    prec, dt = _prec(precision)
+    _dev_tensor(phi, dt, "phi", p)
+    if out is None:
+        out = torch.empty_like(phi)
+    else:
+        _dev_tensor(out, dt, "out", p)
+    sp = None
+    if scalars_out is not None:
+        if not (isinstance(scalars_out, torch.Tensor) and scalars_out.is_cuda and scalars_out.dtype == torch.float64
+                and scalars_out.is_contiguous() and scalars_out.numel() >= 10):
+            raise TypeError("scalars_out must be a contiguous CUDA float64 tensor of at least 10 elements")
+        sp = C.c_void_p(scalars_out.data_ptr())
+    ps = problem_struct(p, v)
+    _check(N.lib().gpe_apply_h_noalloc(context(phi.device.index), C.byref(ps), prec, C.c_void_p(phi.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), sp), "gpe_apply_h_noalloc")
+    return out
+
+
 def _prec(precision):
     prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
     return prec, (torch.complex128 if prec == N.GPE_PREC_FP64 else torch.complex64)

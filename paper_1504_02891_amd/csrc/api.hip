@@ -275,32 +275,66 @@ void set_default(gpe_options* o) {
 // ---------------------------------------------------------------------------
 // apply_h / hess_vec
 // ---------------------------------------------------------------------------
+// Geometry of the stand-alone passes (no allocation): the descriptor's grid
+// fields and tiles, each pass's launch shape, the number of last-pass
+// partial sums (one per wavefront) and of residual blocks.
+struct ApplyShape {
+  Geom g[3];
+  int nsum, nr;
+};
+int apply_shape(const gpe_problem* prob, int fp64, ProbDev* d, double* vaxis, ApplyShape* sh) {
+  CHK(build_prob(prob, d, vaxis));
+  const size_t elem = fp64 ? 16 : 8;
+  // wider strided tiles (more columns per row segment) once the grid is large
+  const int th = d->m >= ((int64_t)1 << 20) ? 256 : kApplyThreads;
+  for (int ax = 0; ax < d->dim; ++ax) {
+    sh->g[ax] = pass_geom(*d, ax, ax > 0, th, elem);
+    if (d->dim == 1) sh->g[ax] = pass_geom(*d, 0, false, 64, elem);
+    d->tiles[ax] = sh->g[ax].tiles;
+    d->lanes[ax] = sh->g[ax].lanes;
+  }
+  const Geom& gl = sh->g[d->dim - 1];
+  sh->nsum = gl.tiles * ((gl.threads + 63) / 64);
+  sh->nr = (int)std::min<int64_t>((d->m + 255) / 256, fp64 ? 1024 : 2048);   // residual blocks
+  return GPE_OK;
+}
+
+// Enqueue the passes (and, for H(phi)phi, the residual and scalar kernels)
+// with the descriptor `P` already in device memory; `out` receives the ten
+// scalars of gpe_apply_h (device), `tot` the chunk totals, `rpart` the
+// residual partials.
+int enqueue_apply(gpe_ctx* c, const ProbDev& d, const ApplyShape& sh, const ProbDev* P, int fp64,
+                  const ApplyArgs& a, double* tot, double* rpart, double* out) {
+  const void* tw = fp64 ? c->twd : c->twf;
+  const Geom* g = sh.g;
+  if (d.dim == 1) {
+    launch_apply_pass(c->s, R_SOLO, fp64, g[0].tiles, g[0].threads, g[0].smem, P, a, tw);
+  } else {
+    launch_apply_pass(c->s, R_FIRST, fp64, g[0].tiles, g[0].threads, g[0].smem, P, a, tw);
+    if (d.dim == 3) launch_apply_pass(c->s, R_MID, fp64, g[1].tiles, g[1].threads, g[1].smem, P, a, tw);
+    launch_apply_pass(c->s, R_FINAL, fp64, g[d.dim - 1].tiles, g[d.dim - 1].threads, g[d.dim - 1].smem, P, a, tw);
+  }
+  HIPCHK(hipGetLastError());
+  if (a.kind == 0) {
+    launch_apply_resid(c->s, sh.nr, P, sh.nsum, a.in, a.out, rpart, tot, fp64);
+    launch_apply_finalize(c->s, P, tot, rpart, sh.nr, out);
+    HIPCHK(hipGetLastError());
+  }
+  return GPE_OK;
+}
+
 int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a, double* scalars) {
   ProbDev d;
   std::vector<double> vaxis(3 * kMaxN);
-  CHK(build_prob(prob, &d, vaxis.data()));
+  ApplyShape sh;
+  CHK(apply_shape(prob, fp64, &d, vaxis.data(), &sh));
   const size_t elem = fp64 ? 16 : 8;
-  Geom g[3];
-  int maxt = 1;
-  // wider strided tiles (more columns per row segment) once the grid is large
-  const int th = d.m >= ((int64_t)1 << 20) ? 256 : kApplyThreads;
-  for (int ax = 0; ax < d.dim; ++ax) {
-    g[ax] = pass_geom(d, ax, ax > 0, th, elem);
-    if (d.dim == 1) g[ax] = pass_geom(d, 0, false, 64, elem);
-    d.tiles[ax] = g[ax].tiles;
-    d.lanes[ax] = g[ax].lanes;
-    maxt = std::max(maxt, g[ax].tiles);
-  }
   void *t, *part, *vax, *pd, *rpart, *out;
   CHK(ws_get(c, WS_APPLY_T, (size_t)d.m * elem, &t));
-  // one partial per wavefront of the last pass
-  const Geom& gl = g[d.dim - 1];
-  const int nsum = gl.tiles * ((gl.threads + 63) / 64);
-  CHK(ws_get(c, WS_APPLY_PART, (size_t)nsum * SA_COUNT * sizeof(double), &part));
+  CHK(ws_get(c, WS_APPLY_PART, (size_t)sh.nsum * SA_COUNT * sizeof(double), &part));
   CHK(ws_get(c, WS_APPLY_VAXIS, vaxis.size() * sizeof(double), &vax));
   CHK(ws_get(c, WS_APPLY_PROB, sizeof(ProbDev), &pd));
-  const int nr = (int)std::min<int64_t>((d.m + 255) / 256, fp64 ? 1024 : 2048);   // residual blocks
-  CHK(ws_get(c, WS_APPLY_RPART, (size_t)nr * SR_COUNT * sizeof(double), &rpart));
+  CHK(ws_get(c, WS_APPLY_RPART, (size_t)sh.nr * SR_COUNT * sizeof(double), &rpart));
   CHK(ws_get(c, WS_APPLY_OUT, (16 + SA_COUNT * 16) * sizeof(double), &out));   // scalars, then chunk totals
   d.t = t;
   d.partF = (double*)part;
@@ -318,28 +352,13 @@ int run_apply(gpe_ctx* c, const gpe_problem* prob, int fp64, const ApplyArgs& a,
     CHK(upload(c, pd, &d, sizeof(d), vb));
     c->apply_key.swap(key);
   }
-  const void* tw = fp64 ? c->twd : c->twf;
-  const ProbDev* P = (const ProbDev*)pd;
-  if (d.dim == 1) {
-    launch_apply_pass(c->s, R_SOLO, fp64, g[0].tiles, g[0].threads, g[0].smem, P, a, tw);
-  } else {
-    launch_apply_pass(c->s, R_FIRST, fp64, g[0].tiles, g[0].threads, g[0].smem, P, a, tw);
-    if (d.dim == 3) launch_apply_pass(c->s, R_MID, fp64, g[1].tiles, g[1].threads, g[1].smem, P, a, tw);
-    launch_apply_pass(c->s, R_FINAL, fp64, g[d.dim - 1].tiles, g[d.dim - 1].threads, g[d.dim - 1].smem, P, a, tw);
-  }
-  HIPCHK(hipGetLastError());
-  if (a.kind == 0) {
-    double* tot = (double*)out + 16;
-    launch_apply_resid(c->s, nr, P, nsum, a.in, a.out, (double*)rpart, tot, fp64);
-    launch_apply_finalize(c->s, P, tot, (const double*)rpart, nr, (double*)out);
-    HIPCHK(hipGetLastError());
-    if (scalars) {
-      void* pin;
-      CHK(pinned_get(c, 16 * sizeof(double), &pin));
-      HIPCHK(hipMemcpyAsync(pin, out, 10 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-      HIPCHK(hipStreamSynchronize(c->s));
-      std::memcpy(scalars, pin, 10 * sizeof(double));
-    }
+  CHK(enqueue_apply(c, d, sh, (const ProbDev*)pd, fp64, a, (double*)out + 16, (double*)rpart, (double*)out));
+  if (a.kind == 0 && scalars) {
+    void* pin;
+    CHK(pinned_get(c, 16 * sizeof(double), &pin));
+    HIPCHK(hipMemcpyAsync(pin, out, 10 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    std::memcpy(scalars, pin, 10 * sizeof(double));
   }
   return GPE_OK;
 }
@@ -974,6 +993,8 @@ int gpe_ctx_create(gpe_ctx** out, int device, void* stream) {
       twd[2 * m] = cr; twd[2 * m + 1] = ci;
       twf[2 * m] = (float)cr; twf[2 * m + 1] = (float)ci;
     }
+    // the device's copy of the no-allocation scratch (this device is current)
+    if (noalloc_init(device) != 0) { rc = GPE_EDEVICE; break; }
     if (hipMalloc(&c->twd, twd.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->twf, twf.size() * sizeof(float)) != hipSuccess) { rc = GPE_ENOMEM; break; }
     if (hipMemcpy(c->twd, twd.data(), twd.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1016,6 +1037,50 @@ int gpe_apply_h(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const vo
   CHK(begin_call(c));
   ApplyArgs a{0, 0.0, phi, nullptr, h_phi};
   CHK(run_apply(c, prob, precision == GPE_PREC_FP64, a, scalars));
+  return end_call(c);
+}
+
+int gpe_apply_h_noalloc(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const void* phi, void* h_phi,
+                        double* scalars_dev) {
+  if (!c || !prob || !phi || !h_phi || phi == h_phi) return GPE_EINVAL;
+  if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
+  const int fp64 = precision == GPE_PREC_FP64;
+  ProbDev d;
+  ApplyShape sh;
+  CHK(apply_shape(prob, fp64, &d, nullptr, &sh));
+  // the fixed scratch: descriptor, tables, scalars, partial sums, accumulator
+  const size_t part_b = kNoAllocAlign((size_t)sh.nsum * SA_COUNT * sizeof(double));
+  const size_t rpart_b = kNoAllocAlign((size_t)sh.nr * SR_COUNT * sizeof(double));
+  const size_t t_b = kNoAllocAlign((size_t)d.m * (fp64 ? 16 : 8));
+  if (d.m > kNoAllocMaxPoints || part_b > kNoAllocPart || rpart_b > kNoAllocRpart || t_b > kNoAllocT) {
+    g_last_error = "gpe_apply_h_noalloc: " + std::to_string(d.m) + " grid points exceed the fixed scratch (at most " +
+                   std::to_string(kNoAllocMaxPoints) + ")";
+    return GPE_EUNSUPPORTED;
+  }
+  HIPCHK(hipSetDevice(c->device));
+  char* base = noalloc_scratch(c->device);
+  if (!base) {
+    g_last_error = "gpe_apply_h_noalloc: the device's scratch was not set up";
+    return GPE_EDEVICE;
+  }
+  const size_t o_v = kNoAllocDesc, o_out = o_v + kNoAllocVaxis, o_part = o_out + kNoAllocOut,
+               o_rpart = o_part + kNoAllocPart, o_t = o_rpart + kNoAllocRpart;
+  d.t = base + o_t;
+  d.part1 = d.partF = (double*)(base + o_part);
+  d.v_axis = (const double*)(base + o_v);
+  VAxisParams vp;
+  for (int i = 0; i < 3; ++i) vp.gamma[i] = prob->gamma[i];
+  vp.amp = prob->lattice_amp;
+  vp.k = prob->lattice_k;
+  // stream order as in every entry point (no staging buffer is involved)
+  HIPCHK(hipEventRecord(c->ev_in, c->user));
+  HIPCHK(hipStreamWaitEvent(c->s, c->ev_in, 0));
+  launch_setup_desc(c->s, d, vp, (ProbDev*)base, (double*)(base + o_v));
+  HIPCHK(hipGetLastError());
+  double* out = (double*)(base + o_out);
+  ApplyArgs a{0, 0.0, phi, nullptr, h_phi};
+  CHK(enqueue_apply(c, d, sh, (const ProbDev*)base, fp64, a, out + 16, (double*)(base + o_rpart),
+                    scalars_dev ? scalars_dev : out));
   return end_call(c);
 }
 

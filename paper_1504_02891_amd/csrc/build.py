@@ -43,7 +43,7 @@ def units():
                         [f"-DGPE_ROLE={role}", f"-DGPE_PREC64={prec}"]))
             out.append(("k_apply_role.hip", f"apply_r{role}_p{prec}",
                         [f"-DGPE_ROLE={role}", f"-DGPE_FP64={prec}"]))
-    for name in ("k_step", "k_dispatch", "api"):
+    for name in ("k_step", "k_dispatch", "k_noalloc", "api"):
         out.append((f"{name}.hip", name, []))
     return out
 

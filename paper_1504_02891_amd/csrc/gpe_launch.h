@@ -33,6 +33,12 @@ void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void*
                     double* part, double* coeffs, int fp64);
 // per-block max |Im x_i| of a complex128 array (part[nblk])
 void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* part);
+// Fixed scratch of the no-allocation entry point (k_noalloc.hip):
+// noalloc_init looks up the device's copy of the array (with `device`
+// current; 0 or a hipError_t), noalloc_scratch returns it (null before init).
+int noalloc_init(int device);
+char* noalloc_scratch(int device);
+void launch_setup_desc(hipStream_t s, const ProbDev& d, const VAxisParams& vp, ProbDev* dst, double* vaxis);
 void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
                          const void* twd);
 }  // namespace gpe

@@ -138,6 +138,28 @@ inline int lds_elems_host(int n, int lanes, bool strided) {
   return strided ? n * (lanes + 1) : lanes * (n + n / 16);
 }
 
+// Parameters of the analytic trap + lattice tables (computed on the device
+// by the no-allocation entry point).
+struct VAxisParams {
+  double gamma[3], amp, k;
+};
+
+// Largest grid of gpe_apply_h_noalloc and the bytes of its fixed scratch:
+// descriptor, potential tables, scalars and chunk totals, last-pass partial
+// sums (at most one per 64 transform points plus one per tile), residual
+// partials (at most 2048 blocks x 6 slots) and the pass accumulator (complex
+// float64), each piece 256-byte aligned.
+constexpr int64_t kNoAllocMaxPoints = (int64_t)1 << 21;
+constexpr size_t kNoAllocAlign(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNoAllocDesc = 1024;
+constexpr size_t kNoAllocVaxis = kNoAllocAlign(3 * 1024 * sizeof(double));
+constexpr size_t kNoAllocOut = kNoAllocAlign(64 * sizeof(double));
+constexpr size_t kNoAllocPart = kNoAllocAlign((size_t)(kNoAllocMaxPoints / 16 + 8192) * 3 * sizeof(double));
+constexpr size_t kNoAllocRpart = kNoAllocAlign(2048 * 6 * sizeof(double));
+constexpr size_t kNoAllocT = kNoAllocAlign((size_t)kNoAllocMaxPoints * 16);
+constexpr size_t kNoAllocBytes = kNoAllocDesc + kNoAllocVaxis + kNoAllocOut + kNoAllocPart + kNoAllocRpart + kNoAllocT;
+static_assert(sizeof(ProbDev) <= kNoAllocDesc, "the descriptor fits its scratch slot");
+
 // Arguments of the stand-alone apply passes.
 // kind 0: H(phi) phi in phi units; kind 1: Hessian-vector product in X units.
 struct ApplyArgs {
