@@ -170,6 +170,7 @@ int build_prob(const gpe_problem* p, ProbDev* d, double* vaxis) {
       d->lo[i] = p->lo[i];
       d->h[i] = box / p->n[i];
       d->x0[i] = dirichlet ? p->lo[i] + d->h[i] : p->lo[i];
+      d->ctr[i] = 0.5 * (p->lo[i] + p->hi[i]);
       d->len[i] = sine ? 2.0 * box : box;
       hvol *= d->h[i];
     } else {
@@ -197,7 +198,7 @@ int build_prob(const gpe_problem* p, ProbDev* d, double* vaxis) {
       for (int j = 0; j < kMaxN; ++j) {
         double v = 0.0;
         if (i < p->dim && j < d->n[i]) {
-          const double x = d->x0[i] + d->h[i] * j;
+          const double x = grid_coord(*d, i, j);
           const double s = std::sin(p->lattice_k * x);
           v = 0.5 * p->gamma[i] * p->gamma[i] * x * x + p->lattice_amp * s * s;
         }

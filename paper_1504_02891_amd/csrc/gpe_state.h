@@ -83,6 +83,8 @@ struct ProbDev {
   int32_t pad_r;
   double lo[3], h[3], len[3];   // len: period of the transformed line (b-a, or 2(b-a) for sine)
   double x0[3];          // coordinate of array index 0 (lo, or lo + h for sine and finite differences)
+  double ctr[3];         // centre of the box (lo + hi) / 2: Dirichlet grids take the coordinates of
+                         // their points as ctr + (j + 1 - N/2) h, mirror images of each other exactly
   double beta, omega, hvol, sqrt_hvol, alpha;
   const double* v_arr;   // explicit V (float64), or null
   const double* v_axis;  // [3][kMaxN]: V = v_axis[0][x] + v_axis[1][y] + v_axis[2][z]
@@ -101,6 +103,16 @@ struct ProbDev {
   const void* user_in;   // apply / init input
   void* user_out;        // apply output
 };
+
+// Coordinate of array index j on axis i in the potential tables.  On a
+// Dirichlet grid (N = n + 1 intervals) the points j and N - 2 - j are mirror
+// images about the box centre, and this form makes their coordinates exact
+// negatives relative to it, so a mirror-symmetric trap gives a mirror-symmetric
+// table to the last bit; periodic grids take lo + j h.
+inline __host__ __device__ double grid_coord(const ProbDev& d, int i, int j) {
+  if (d.bc == BC_FOURIER) return d.x0[i] + d.h[i] * j;
+  return d.ctr[i] + d.h[i] * (double)(j + 1 - (d.n[i] + 1) / 2);
+}
 
 // Per-problem solver state, written only by the step kernel.
 struct SolverState {

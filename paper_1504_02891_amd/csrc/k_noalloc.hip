@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(256) k_setup_desc(ProbDev d, VAxisParams vp, P
     const int i = idx / kMaxN, j = idx % kMaxN;
     double v = 0.0;
     if (i < d.dim && j < d.n[i]) {
-      const double x = d.x0[i] + d.h[i] * j;
+      const double x = grid_coord(d, i, j);
       const double s = sin(vp.k * x);
       v = 0.5 * vp.gamma[i] * vp.gamma[i] * x * x + vp.amp * s * s;
     }

@@ -16,10 +16,12 @@ __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict
   ProbDev P = probs[blockIdx.x];
   pin_reg(P.part1); pin_reg(P.partF); pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
   pin_reg(P.dim); pin_reg(P.sqrt_hvol);
-  if (states[blockIdx.x].mode == M_IDLE) return;
+  // the partial sums are reduced before the state is known to need them, so
+  // that their loads go out with the state's
   if (threadIdx.x < 64) touch_lines(states + blockIdx.x);
   double r1[S1_COUNT], rf[SF_COUNT];
   step_reductions(P.part1, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red);
+  if (states[blockIdx.x].mode == M_IDLE) return;
   if (threadIdx.x == 0) {
     SolverState L = states[blockIdx.x];
     step_logic(P, L, r1, rf, prec64);

@@ -144,7 +144,66 @@ __device__ __forceinline__ void fd_stencil(const ProbDev& P, int ax, const Tile<
     const cx<CT> lft = data[T.mp.idx(T.lane, p > 0 ? p - 1 : 0, N)];
     const cx<CT> rgt = data[T.mp.idx(T.lane, p < N - 1 ? p + 1 : N - 1, N)];
     const cx<CT> l = p > 0 ? lft : zero, r = p < N - 1 ? rgt : zero;
-    v[e] = c * (((CT)2 * v[e] - l) - r);
+    // the neighbours' sum first: a line that is odd or even about its
+    // centre keeps that parity to the last bit
+    v[e] = c * ((CT)2 * v[e] - (l + r));
+  }
+}
+
+// Mirror parity of sine lines about the box centre: interior positions
+// p = 1 .. H-1 of the odd extension (H = N/2) mirror to H - p.  The FFT of
+// the extension keeps a line's parity only up to rounding, and an excited
+// state (§4.4) is a saddle point held by its parity alone, so a line that
+// enters the transform exactly odd (or even) leaves it as the odd (even) part
+// of the result, which equals the result up to that rounding; other lines are
+// left as they are.  sine_parity_in records per line whether the input is
+// exactly odd (bit 0) or even (bit 1); sine_parity_out applies it.  Every
+// thread of the workgroup must call both (barriers); both use the LDS line
+// area, sine_parity_in before the first transform stage (which starts with a
+// barrier), sine_parity_out after the last.
+__device__ __forceinline__ int* sine_flag_store() {
+  __shared__ int f[64];   // lines per tile of a sine pass: at most 256 threads / 4
+  return f;
+}
+template <int N, typename CT>
+__device__ __forceinline__ void sine_parity_in(const Tile<N>& T, const cx<CT>* v, cx<CT>* data) {
+  constexpr int H = N / 2;
+  int* flags = sine_flag_store();
+  __syncthreads();       // nobody still reads the LDS lines
+  if (T.t == 0) flags[T.lane] = 3;
+#pragma unroll
+  for (int e = 0; e < Tile<N>::E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
+  __syncthreads();
+  int bad = 0;
+#pragma unroll
+  for (int e = 0; e < Tile<N>::E; ++e) {
+    const int p = T.pos(e);
+    if (p > 0 && p < H) {
+      const cx<CT> q = data[T.mp.idx(T.lane, H - p, N)];
+      if (!(v[e].re == -q.re && v[e].im == -q.im)) bad |= 1;
+      if (!(v[e].re == q.re && v[e].im == q.im)) bad |= 2;
+    }
+  }
+  if (bad) atomicAnd(&flags[T.lane], ~bad);
+}
+template <int N, typename CT>
+__device__ __forceinline__ void sine_parity_out(const Tile<N>& T, cx<CT>* v, cx<CT>* data) {
+  constexpr int H = N / 2;
+  const int* flags = sine_flag_store();
+  __syncthreads();       // the last transform stage has read its LDS lines
+#pragma unroll
+  for (int e = 0; e < Tile<N>::E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
+  __syncthreads();
+  const int f = flags[T.lane];
+  if (f == 0) return;
+  const CT half = (CT)0.5;
+#pragma unroll
+  for (int e = 0; e < Tile<N>::E; ++e) {
+    const int p = T.pos(e);
+    if (p > 0 && p < H) {
+      const cx<CT> q = data[T.mp.idx(T.lane, H - p, N)];
+      v[e] = (f & 1) ? half * (v[e] - q) : half * (v[e] + q);
+    }
   }
 }
 
@@ -159,6 +218,7 @@ __device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const
     fd_stencil<N, CT>(P, ax, T, v, lds);
     return;
   }
+  if (T.sine) sine_parity_in<N, CT>(T, v, lds + N);
   line_fft<N, false>(v, T.t, T.lane, T.mp, lds + N, lds);
   const CT rc = (CT)T.rot(P);
   const CT tpl = (CT)(6.283185307179586477 / pick3(P.len, ax));
@@ -172,6 +232,7 @@ __device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const
 template <int N, typename CT>
 __device__ __forceinline__ void spectral_inverse(const Tile<N>& T, cx<CT>* v, cx<CT>* lds) {
   if (!T.fd) line_fft<N, true>(v, T.t, T.lane, T.mp, lds + N, lds);
+  if (T.sine) sine_parity_out<N, CT>(T, v, lds + N);
 }
 template <int N, typename CT>
 __device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
@@ -556,31 +617,66 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, 
   }
 }
 
-// STEP_FUSED: the scalar step of the previous evaluation, run by every
-// workgroup of the first pass on its own copy of the state (each reduces the
-// same partial sums in the same order, so every copy gets the same bits);
-// the workgroup of tile 0 stores the new state for the later passes and the
-// host.  `part1_prev` holds the previous evaluation's first-pass partials.
-// Every thread of the workgroup must call it; S is updated in every thread.
-__device__ __forceinline__ void fused_step(const ProbDev& P, SolverState& S, const double* part1_prev,
-                                           SolverState* out, bool writer, int prec64, double* red) {
-  __shared__ SolverState sh;
-  if (S.pending && S.mode != M_IDLE) {
-    double r1[S1_COUNT], rf[SF_COUNT];
-    step_reductions(part1_prev, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red);
-    if (threadIdx.x == 0) {
-      SolverState L = S;
-      step_logic(P, L, r1, rf, prec64);
-      L.pending = L.mode != M_IDLE ? 1 : 0;
-      sh = L;
-      if (writer) *out = L;
-    }
-    __syncthreads();
-    S = sh;
-  } else {
-    S.pending = S.mode != M_IDLE ? 1 : 0;
-    if (writer && threadIdx.x == 0) *out = S;
+// Every wavefront reduces all first-pass (S1) slots of `part1` (n1 tiles)
+// and final-pass (SF) slots of `partF` (nF tiles) on its own, with every
+// load of every slot in one batch (B per lane) when the tiles allow it; each
+// slot is summed in the order of wave_reduce_partials (lane l takes tiles l,
+// l + 64, ... in turn), so the bits are those of the step kernel's.
+template <int B>
+__device__ __forceinline__ void wave_reduce_all_b(const double* part1, int n1, const double* partF, int nF,
+                                                  double* r1, double* rf) {
+  const int l = threadIdx.x & 63;
+  double v1[B][S1_COUNT], vf[B][SF_COUNT];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int64_t i1 = min(l + 64 * j, n1 - 1), iF = min(l + 64 * j, nF - 1);
+#pragma unroll
+    for (int s = 0; s < S1_COUNT; ++s) v1[j][s] = gld<double>(part1, (int64_t)s * n1 + i1);
+#pragma unroll
+    for (int s = 0; s < SF_COUNT; ++s) vf[j][s] = gld<double>(partF, (int64_t)s * nF + iF);
   }
+#pragma unroll
+  for (int s = 0; s < S1_COUNT; ++s) r1[s] = 0.0;
+#pragma unroll
+  for (int s = 0; s < SF_COUNT; ++s) rf[s] = 0.0;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    if (l + 64 * j < n1)
+#pragma unroll
+      for (int s = 0; s < S1_COUNT; ++s) r1[s] = s == S1_RMAX ? fmax(r1[s], v1[j][s]) : r1[s] + v1[j][s];
+    if (l + 64 * j < nF)
+#pragma unroll
+      for (int s = 0; s < SF_COUNT; ++s) rf[s] = s == SF_SMAX ? fmax(rf[s], vf[j][s]) : rf[s] + vf[j][s];
+  }
+  wave_reduce_k<S1_COUNT>(r1, 1u << S1_RMAX);
+  wave_reduce_k<SF_COUNT>(rf, 1u << SF_SMAX);
+}
+__device__ __forceinline__ void wave_reduce_all(const double* part1, int n1, const double* partF, int nF,
+                                                double* r1, double* rf) {
+  const int n = max(n1, nF);
+  if (n <= 64) wave_reduce_all_b<1>(part1, n1, partF, nF, r1, rf);
+  else if (n <= 128) wave_reduce_all_b<2>(part1, n1, partF, nF, r1, rf);
+  else if (n <= 256) wave_reduce_all_b<4>(part1, n1, partF, nF, r1, rf);
+  else {
+    wave_reduce_partials<S1_COUNT>(part1, n1, 1u << S1_RMAX, r1);
+    wave_reduce_partials<SF_COUNT>(partF, nF, 1u << SF_SMAX, rf);
+  }
+}
+
+// STEP_FUSED: the scalar step of the previous evaluation, run by every
+// wavefront of the first pass on its own (every lane on the same values, so
+// each copy of the state gets the same bits without any exchange); the
+// workgroup of tile 0 stores the new state for the later passes and the
+// host.  `part1_prev` holds the previous evaluation's first-pass partials.
+// The partial sums are read before the state is known to need them, so that
+// their loads go out with the state's.
+__device__ __forceinline__ void fused_step(const ProbDev& P, SolverState& S, const double* part1_prev,
+                                           SolverState* out, bool writer, int prec64) {
+  double r1[S1_COUNT], rf[SF_COUNT];
+  wave_reduce_all(part1_prev, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf);
+  if (S.pending && S.mode != M_IDLE) step_logic(P, S, r1, rf, prec64);
+  S.pending = S.mode != M_IDLE ? 1 : 0;
+  if (writer && threadIdx.x == 0) *out = S;
 }
 
 // The state fields the passes read.
@@ -652,7 +748,7 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   if (par) P.part1 = P.part1x;
   if constexpr (ROLE == R_FIRST) {
     if (P.step_at == STEP_FUSED) {
-      fused_step(P, S, part1_other, st_out + bm.x, bm.y == 0, PREC64 ? 1 : 0, red);
+      fused_step(P, S, part1_other, st_out + bm.x, bm.y == 0, PREC64 ? 1 : 0);
       GPE_PASS_STATE_FIELDS(make_uniform);
       GPE_PASS_STATE_FIELDS(pin_reg);
     }

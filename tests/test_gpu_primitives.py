@@ -289,6 +289,32 @@ def test_apply_h_sine_complex_data(dev, p):
     assert float(np.max(np.abs(out.cpu().numpy() - ref))) <= _bound(p, phi, "fp64")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("dims", [(256, 256), (64, 32, 128)])
+def test_sine_and_fd_passes_keep_mirror_parity(dev, prec, dims):
+    # A field that is exactly odd (or even) under the mirror x -> -x of a
+    # centred box gives an H(phi)phi and a Hessian-vector product that are
+    # exactly odd (even) too, on lines of every axis (§4.4's excited states
+    # are saddle points held by this parity alone).
+    d = len(dims)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    for bc in (W.SINE, W.FD):
+        p = W.Problem(dim=d, n=dims, lo=(-16.0,) * d, hi=(16.0,) * d, bc=bc, beta=500.0, lattice_amp=50.0)
+        f = _real_field(p, 21) + 0.3j * _real_field(p, 22)
+        up = UnifiedProblem(p)
+        for ax in range(d):
+            flip = lambda a: np.flip(a, axis=d - 1 - ax)
+            for sgn in (-1.0, 1.0):
+                g = 0.5 * (f + sgn * flip(f))
+                assert np.array_equal(flip(g), sgn * g)
+                t = torch.from_numpy(g).to(dt).cuda()
+                out = dev.apply_h(p, t, precision=prec)[0].cpu().numpy()
+                assert np.array_equal(flip(out), sgn * out), (bc, ax, sgn, prec)
+                xk = math.sqrt(up.hvol) * (np.abs(g) + 0j)     # complex128, even in every axis
+                s = dev.hess_vec(p, torch.from_numpy(xk).cuda(), t, 0.37, precision=prec).cpu().numpy()
+                assert np.array_equal(flip(s), sgn * s), (bc, ax, sgn, prec, "hess")
+
+
 def test_apply_h_sine_eigenfunction(dev):
     # beta = 0, V = 0: sin(l pi j / N) x sin(m pi k / N) is an eigenvector of
     # the sine operator with eigenvalue (lambda_l^2 + lambda_m^2) / 2
