@@ -236,7 +236,7 @@ def install_plans(api, probs, precs, levels, retune):
                     continue
                 rec = recorded.get(f"{prec} {'x'.join(map(str, key[1]))} {key[2]}")
                 if rec is not None:
-                    api.set_plan(p, prec, rec["threads"], rec["step_at"])
+                    api.set_plan(p, prec, rec["threads"], rec["step_at"], rec.get("elems"))
                     plans[key] = dict(rec, source="recorded")
                 else:
                     plans[key] = dict(api.autotune(p, prec), source="tuned")

@@ -130,7 +130,7 @@ typedef struct gpe_options {
                              (the method on the unit sphere of R^M); otherwise rounding noise in
                              them can grow and lead the iteration to a complex stationary state */
     int32_t threads[3];   /* workgroup size of the x, y, z passes (0 = built-in choice);
-                             a multiple of 64 and of n/8, at most 256 */
+                             a multiple of 64 and of n/elems, at most 256 */
     int32_t step_at;      /* where the scalar step of the solver runs (GPE_STEP_*) */
     int32_t stop_rule;    /* GPE_STOP_RESID (default), GPE_STOP_CRIT1 or GPE_STOP_CRIT2 */
     int32_t monotone;     /* 1: monotone Armijo search, C = F(X_k) (eta = 0); 0: Zhang-Hager */
@@ -150,6 +150,12 @@ typedef struct gpe_options {
                              the most), since the Newton subproblems in FP32 stall near the FP32
                              residual floor.  0 = never (default 1e-4, about ten times the floor
                              of the benchmark grids) */
+    int32_t elems[3];     /* transform points per thread in the x, y, z passes: 8 or 4 (0 = built-in
+                             choice: 4 below 2^20 grid points in all, else 8).  4 gives each line
+                             twice the threads with half the work each (shorter chains where a
+                             pass is latency bound); the workgroup size (threads) must be a multiple
+                             of the line's threads, n/elems */
+    int32_t reserved3;
 } gpe_options;
 
 /* ---- results ------------------------------------------------------------ */
@@ -288,20 +294,23 @@ int gpe_solve_batched(gpe_ctx* ctx, int32_t count, const gpe_problem* probs,
 
 /*
  * Tuning of the launch configuration for one grid (dim, n, bc) and precision:
- * short solves of a synthetic state on that grid time every valid workgroup
- * size per pass (64, 128, 256 threads, a multiple of n/8) and every step
- * placement (GPE_STEP_FUSED up to 512 first-pass workgroups, in 2D and 3D);
- * the fastest plan is kept in the context (one per grid and
+ * short solves of a synthetic state on that grid time 8 and 4 transform
+ * points per thread, every valid workgroup size per pass (64, 128, 256
+ * threads, a multiple of n/points) and every step placement (GPE_STEP_FUSED up
+ * to 512 first-pass workgroups, in 2D and 3D); the fastest plan is kept in
+ * the context (one per grid and
  * precision, replaced by a later call).  Later gpe_solve / gpe_solve_batched /
  * gpe_solve_cascadic calls on a context with a plan for their grid use it
- * wherever their options leave the choice open (threads 0, step_at AUTO).
+ * wherever their options leave the choice open (threads and elems 0, step_at
+ * AUTO).
  * A plan changes the tiling, hence the order of the float64 reductions, not
- * the method.  threads_out[3], step_at_out, us_per_eval_out: HOST, optional
- * (the chosen plan and its time per evaluation in microseconds).  Takes a few
- * hundred milliseconds to seconds; allocates device workspace in the context.
+ * the method.  threads_out[3], elems_out[3], step_at_out, us_per_eval_out:
+ * HOST, optional (the chosen plan and its time per evaluation in
+ * microseconds).  Takes a few hundred milliseconds to seconds; allocates
+ * device workspace in the context.
  */
 int gpe_autotune(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, int32_t* threads_out,
-                 int32_t* step_at_out, double* us_per_eval_out);
+                 int32_t* elems_out, int32_t* step_at_out, double* us_per_eval_out);
 
 /*
  * Keep a given launch plan for the grid of `prob` and `precision` in the
@@ -310,13 +319,14 @@ int gpe_autotune(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, int32
  * later runs tile the grid the same way and take the same bits.
  * threads: HOST int32[3], the workgroup size of the x, y, z passes (entries
  * beyond the problem's dimension ignored), each 64, 128 or 256 and a multiple
- * of the pass's threads per line (the transform length / 8); step_at:
- * GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL or GPE_STEP_FUSED.  GPE_EINVAL for
- * anything else.
+ * of the pass's threads per line (the transform length / elems); elems: HOST
+ * int32[3], the points per thread of each pass (8 or 4), or NULL for 8;
+ * step_at: GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL or GPE_STEP_FUSED.
+ * GPE_EINVAL for anything else.
  * Host only: no device work.
  */
 int gpe_set_plan(gpe_ctx* ctx, const gpe_problem* prob, int32_t precision, const int32_t* threads,
-                 int32_t step_at);
+                 const int32_t* elems, int32_t step_at);
 
 /*
  * Trigonometric prolongation for the cascadic multigrid (Algorithm 3): the

@@ -58,7 +58,7 @@ class Options(C.Structure):
                 ("real_field", C.c_int32), ("threads", C.c_int32 * 3), ("step_at", C.c_int32),
                 ("stop_rule", C.c_int32), ("monotone", C.c_int32), ("eps0", C.c_double),
                 ("crit2_tol", C.c_double), ("switch_window", C.c_int32), ("reserved1", C.c_int32),
-                ("switch_resid", C.c_double)]
+                ("switch_resid", C.c_double), ("elems", C.c_int32 * 3), ("reserved3", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -108,8 +108,9 @@ def lib():
     L.gpe_solve_batched.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(Options), C.POINTER(vp),
                                     C.POINTER(Result)]
     L.gpe_prolong.argtypes = [vp, C.POINTER(Problem), C.POINTER(Problem), vp, vp]
-    L.gpe_autotune.argtypes = [vp, C.POINTER(Problem), i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)]
-    L.gpe_set_plan.argtypes = [vp, C.POINTER(Problem), i32, C.POINTER(i32), i32]
+    L.gpe_autotune.argtypes = [vp, C.POINTER(Problem), i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                               C.POINTER(dbl)]
+    L.gpe_set_plan.argtypes = [vp, C.POINTER(Problem), i32, C.POINTER(i32), C.POINTER(i32), i32]
     L.gpe_solve_cascadic.argtypes = [vp, i32, C.POINTER(Problem), i32, dbl, C.POINTER(Options),
                                      C.POINTER(vp), C.POINTER(vp), C.POINTER(Result)]
     for name in EXPORTS:

@@ -89,6 +89,10 @@ def options(**kw):
     if thr is not None:
         for i, t in enumerate(list(thr)[:3]):
             o.threads[i] = int(t)
+    ept = kw.pop("elems", None)
+    if ept is not None:
+        for i, e in enumerate(list(ept)[:3]):
+            o.elems[i] = int(e)
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
@@ -230,21 +234,24 @@ def autotune(p, precision="mixed", device=0):
     their options leave the choice open.  Returns the plan."""
     prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
     thr = (C.c_int32 * 3)()
+    ept = (C.c_int32 * 3)()
     step = C.c_int32()
     us = C.c_double()
     ps = problem_struct(p)
-    _check(N.lib().gpe_autotune(context(device), C.byref(ps), prec, thr, C.byref(step), C.byref(us)),
+    _check(N.lib().gpe_autotune(context(device), C.byref(ps), prec, thr, ept, C.byref(step), C.byref(us)),
            "gpe_autotune")
-    return {"threads": list(thr), "step_at": step.value, "us_per_eval": us.value}
+    return {"threads": list(thr), "elems": list(ept), "step_at": step.value, "us_per_eval": us.value}
 
 
-def set_plan(p, precision, threads, step_at, device=0):
+def set_plan(p, precision, threads, step_at, elems=None, device=0):
     """Keep a given launch plan (e.g. one returned by ``autotune`` earlier) for
-    the grid of ``p`` in the device's context, as ``autotune`` keeps its own."""
+    the grid of ``p`` in the device's context, as ``autotune`` keeps its own.
+    ``elems``: points per thread of each pass (8 or 4; None for 8)."""
     prec = N.GPE_PREC_FP64 if precision == "fp64" else N.GPE_PREC_MIXED
     thr = (C.c_int32 * 3)(*[int(t) for t in list(threads)[:3]])
+    ept = None if elems is None else (C.c_int32 * 3)(*[int(e) for e in list(elems)[:3]])
     ps = problem_struct(p)
-    _check(N.lib().gpe_set_plan(context(device), C.byref(ps), prec, thr, int(step_at)), "gpe_set_plan")
+    _check(N.lib().gpe_set_plan(context(device), C.byref(ps), prec, thr, ept, int(step_at)), "gpe_set_plan")
 
 
 def prolong(p_coarse, p_fine, phi_c):

@@ -50,7 +50,7 @@ enum WsSlot {
 // A tuned launch configuration (gpe_autotune) for one grid and precision.
 struct TunedPlan {
   int dim, bc, n[3], prec;
-  int threads[3], step_at;
+  int threads[3], elems[3], step_at;
 };
 
 struct gpe_ctx {
@@ -214,11 +214,12 @@ struct Geom {
 };
 
 // Tiling of a pass along axis `ax`: transform lines of N = nl[ax] points,
-// TL = N/kE threads per line, `threads / TL` lines per workgroup.
-Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem) {
+// TL = N/ept threads per line (ept = points per thread, 8 or 4), `threads /
+// TL` lines per workgroup.
+Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem, int ept = kE) {
   Geom g;
   const int N = d.nl[ax];
-  const int TL = N / kE;
+  const int TL = N / ept;
   g.threads = threads < TL ? TL : threads;
   g.lanes = g.threads / TL;
   const int64_t cols = d.m / d.n[ax];
@@ -226,6 +227,14 @@ Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem)
   // twiddle table (N entries) + line data
   g.smem = ((size_t)N + (size_t)gpe::lds_elems_host(N, g.lanes, strided)) * elem;
   return g;
+}
+
+// Built-in points per thread: 4 while the problems are small enough to be
+// bound by the latency of the passes (shorter per-thread chains), else 8.
+int default_elems(const std::vector<ProbDev>& pd) {
+  int64_t m = 0;
+  for (const ProbDev& d : pd) m += d.m;
+  return m < ((int64_t)1 << 20) ? 4 : kE;
 }
 
 // Built-in workgroup size: one wavefront for 1D (a single line), 256 threads
@@ -263,6 +272,8 @@ void set_default(gpe_options* o) {
   o->profile = 0;
   o->real_field = -1;
   o->threads[0] = o->threads[1] = o->threads[2] = 0;
+  o->elems[0] = o->elems[1] = o->elems[2] = 0;
+  o->reserved3 = 0;
   o->step_at = GPE_STEP_AUTO;
   o->stop_rule = GPE_STOP_RESID;
   o->monotone = 0;
@@ -404,6 +415,8 @@ int check_options(const gpe_options* o) {
   if (o->chunk < 1 || o->chunk > 4096) return GPE_EINVAL;
   if (o->step_at < GPE_STEP_AUTO || o->step_at > GPE_STEP_FUSED) return GPE_EINVAL;
   if (o->real_field < -1 || o->real_field > 1) return GPE_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (o->elems[a] != 0 && o->elems[a] != 4 && o->elems[a] != 8) return GPE_EINVAL;
   if (o->stop_rule < GPE_STOP_RESID || o->stop_rule > GPE_STOP_CRIT2) return GPE_EINVAL;
   if (o->monotone != 0 && o->monotone != 1) return GPE_EINVAL;
   if (!(o->eps0 >= 0.0) || !(o->crit2_tol >= 0.0) || o->switch_window < 0 ||
@@ -462,13 +475,17 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       }
       for (int i = 0; i < count && tp; ++i)
         for (int a = 0; a < probs[i].dim; ++a) {
-          const int tl = (probs[i].bc == GPE_BC_SINE ? 2 * probs[i].n[a] : probs[i].n[a]) / kE;
+          const int tl = (probs[i].bc == GPE_BC_SINE ? 2 * probs[i].n[a] : probs[i].n[a]) / tp->elems[a];
           if (tl < 1 || tp->threads[a] < tl || tp->threads[a] % tl != 0) tp = nullptr;
           if (!tp) break;
         }
     }
-    if (tp && o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0)
-      for (int a = 0; a < 3; ++a) o.threads[a] = tp->threads[a];
+    if (tp && o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0 && o.elems[0] == 0 && o.elems[1] == 0 &&
+        o.elems[2] == 0)
+      for (int a = 0; a < 3; ++a) {
+        o.threads[a] = tp->threads[a];
+        o.elems[a] = tp->elems[a];
+      }
     if (tp && all && o.step_at == GPE_STEP_AUTO) o.step_at = tp->step_at;
   }
   const int prec64 = o.precision == GPE_PREC_FP64;
@@ -481,19 +498,22 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     CHK(build_prob(&probs[i], &pd[i], &vaxis[(size_t)i * 3 * kMaxN]));
     if (pd[i].dim != dim) return GPE_EINVAL;
   }
-  // geometry of each pass for each problem
+  // geometry of each pass for each problem: points per thread (8, or 4 for
+  // latency-bound problems by default) and workgroup size
   std::vector<Geom> geo((size_t)count * 3);
   size_t smem[3] = {0, 0, 0};
+  int ept[3];
   for (int ax = 0; ax < 3; ++ax) {
+    ept[ax] = o.elems[ax] ? o.elems[ax] : default_elems(pd);
     const int th = o.threads[ax];
     if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
     for (int i = 0; i < count && th != 0 && ax < dim; ++i)
-      if (th % (pd[i].nl[ax] / kE) != 0) return GPE_EINVAL;
+      if (th % (pd[i].nl[ax] / ept[ax]) != 0 || pd[i].nl[ax] / ept[ax] > 256) return GPE_EINVAL;
   }
   for (int i = 0; i < count; ++i)
     for (int ax = 0; ax < dim; ++ax) {
       const int th = o.threads[ax] ? o.threads[ax] : default_threads(pd, dim);
-      Geom g = pass_geom(pd[i], ax, ax > 0, th, 16);
+      Geom g = pass_geom(pd[i], ax, ax > 0, th, 16, ept[ax]);
       geo[(size_t)i * 3 + ax] = g;
       pd[i].tiles[ax] = g.tiles;
       pd[i].lanes[ax] = g.lanes;
@@ -1127,7 +1147,7 @@ int gpe_solve_batched(gpe_ctx* c, int32_t count, const gpe_problem* probs, const
 }
 
 int gpe_set_plan(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const int32_t* threads,
-                 int32_t step_at) {
+                 const int32_t* elems, int32_t step_at) {
   if (!c || !prob || !threads) return GPE_EINVAL;
   if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
   if (step_at != GPE_STEP_LAST_GROUP && step_at != GPE_STEP_KERNEL && step_at != GPE_STEP_FUSED) return GPE_EINVAL;
@@ -1136,9 +1156,12 @@ int gpe_set_plan(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const i
   TunedPlan tp{};
   for (int a = 0; a < 3; ++a) {
     if (a >= d.dim) continue;
-    const int tl = d.nl[a] / kE, t = threads[a];
+    const int e = elems ? elems[a] : kE;
+    if (e != 4 && e != 8) return GPE_EINVAL;
+    const int tl = d.nl[a] / e, t = threads[a];
     if ((t != 64 && t != 128 && t != 256) || t < tl || t % tl != 0) return GPE_EINVAL;
     tp.threads[a] = t;
+    tp.elems[a] = e;
   }
   tp.step_at = step_at;
   tp.dim = prob->dim;
@@ -1150,7 +1173,7 @@ int gpe_set_plan(gpe_ctx* c, const gpe_problem* prob, int32_t precision, const i
 }
 
 int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t* threads_out,
-                 int32_t* step_at_out, double* us_per_eval_out) {
+                 int32_t* elems_out, int32_t* step_at_out, double* us_per_eval_out) {
   if (!c || !prob) return GPE_EINVAL;
   if (precision != GPE_PREC_FP64 && precision != GPE_PREC_MIXED) return GPE_EINVAL;
   ProbDev d;
@@ -1174,14 +1197,17 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
   }
   void* buf;
   CHK(ws_get(c, WS_TUNE, m * 16, &buf));
-  // candidates: workgroup sizes per pass, then the step placement
-  std::vector<int> cand[3];
-  for (int a = 0; a < 3; ++a) {
-    if (a >= d.dim) { cand[a].push_back(0); continue; }
-    const int tl = d.nl[a] / kE;
-    for (int t : {64, 128, 256})
-      if (t >= tl && t % tl == 0) cand[a].push_back(t);
-  }
+  // candidates: points per thread (the same in every pass), workgroup
+  // sizes per pass, then the step placement
+  auto cands = [&](int ept, std::vector<int>* cand) {
+    for (int a = 0; a < 3; ++a) {
+      cand[a].clear();
+      if (a >= d.dim) { cand[a].push_back(0); continue; }
+      const int tl = d.nl[a] / ept;
+      for (int t : {64, 128, 256})
+        if (t >= tl && t % tl == 0) cand[a].push_back(t);
+    }
+  };
   gpe_options o;
   set_default(&o);
   o.precision = precision;
@@ -1195,11 +1221,16 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
   o.switch_resid = 0.0;
   double best = INFINITY;
   TunedPlan bp{};
+  std::vector<int> cand[3];
+  for (int ept : {kE, 4}) {
+    cands(ept, cand);
+    for (int a = 0; a < 3; ++a) o.elems[a] = a < d.dim ? ept : 0;
   for (int t0 : cand[0])
     for (int t1 : cand[1])
       for (int t2 : cand[2])
         for (int sa : {GPE_STEP_LAST_GROUP, GPE_STEP_KERNEL, GPE_STEP_FUSED}) {
-          if (sa == GPE_STEP_FUSED && (d.dim == 1 || d.m / d.n[0] / (t0 / (d.nl[0] / kE)) > kFusedMaxTiles)) continue;
+          if (sa == GPE_STEP_FUSED && (d.dim == 1 || d.m / d.n[0] / (t0 / (d.nl[0] / ept)) > kFusedMaxTiles)) continue;
+          if (sa != GPE_STEP_LAST_GROUP && d.dim == 1) continue;     // a 1D solve always steps in its pass
           o.threads[0] = t0; o.threads[1] = t1; o.threads[2] = t2;
           o.step_at = sa;
           double us = INFINITY;
@@ -1215,9 +1246,11 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
           if (us < best) {
             best = us;
             bp.threads[0] = t0; bp.threads[1] = t1; bp.threads[2] = t2;
+            for (int a = 0; a < 3; ++a) bp.elems[a] = a < d.dim ? ept : kE;
             bp.step_at = sa;
           }
         }
+  }
   bp.dim = prob->dim;
   bp.bc = prob->bc;
   bp.prec = precision;
@@ -1225,6 +1258,8 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
   keep_plan(c, *prob, bp);
   if (threads_out)
     for (int a = 0; a < 3; ++a) threads_out[a] = bp.threads[a];
+  if (elems_out)
+    for (int a = 0; a < 3; ++a) elems_out[a] = bp.elems[a];
   if (step_at_out) *step_at_out = bp.step_at;
   if (us_per_eval_out) *us_per_eval_out = best;
   return GPE_OK;

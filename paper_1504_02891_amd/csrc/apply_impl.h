@@ -9,15 +9,14 @@ namespace gpe {
 
 // KIND 0: H(phi) phi with the energy sums; KIND 1: Hessian-vector product.
 // Only the epilogue roles (FINAL, SOLO) depend on KIND.
-template <int N, int ROLE, typename T, int KIND>
+template <int N, int E, int ROLE, typename T, int KIND>
 __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A, int tile, cx<T>* lds,
                                            const cx<T>* tw1024, double* red) {
-  constexpr int E = Tile<N>::E;
   constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   const int ax = role_axis(ROLE, P.dim);
   constexpr bool EPI = (ROLE == R_FINAL || ROLE == R_SOLO);
   constexpr bool HESS = EPI && KIND == 1;
-  const Tile<N> Tl(P, ax, HAS_T, tile);
+  const Tile<N, E> Tl(P, ax, HAS_T, tile);
   TwiddleFetch<N, T> twf;
   twf.fetch(tw1024);
   // loads: the input first; the accumulator, X_k (Hessian-vector) and the
@@ -48,8 +47,8 @@ __device__ __forceinline__ void apply_tile(const ProbDev& P, const ApplyArgs& A,
   }
   if constexpr (LOADS_AT == 0) late_loads();
   twf.store(lds);
-  spectral_forward<N, T>(P, ax, Tl, v, lds);
-  spectral_inverse<N, T>(Tl, v, lds);
+  spectral_forward<N, E, T>(P, ax, Tl, v, lds);
+  spectral_inverse<N, E, T>(Tl, v, lds);
   if constexpr (LOADS_AT == 2) late_loads();
   if constexpr (ROLE == R_FIRST) {
 #pragma unroll
@@ -110,18 +109,21 @@ __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ 
   __shared__ double red[SA_COUNT * 16];
   const ProbDev P = probs[0];     // local copy: one batch of loads
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  const int n = pick3(P.nl, role_axis(ROLE, P.dim));
+  const int ax = role_axis(ROLE, P.dim);
+  const int n = pick3(P.nl, ax);
+  const bool e4 = n * pick3(P.lanes, ax) == 4 * (int)blockDim.x;    // points per thread 4 or 8
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+#define GPE_APPLY_CASE(NN)                                                      \
+  case NN:                                                                      \
+    if (e4) apply_tile<NN, 4, ROLE, T, KIND>(P, A, tile, lds, tw, red);         \
+    else apply_tile<NN, 8, ROLE, T, KIND>(P, A, tile, lds, tw, red);            \
+    break;
   switch (n) {
-    case 16: apply_tile<16, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
-    case 32: apply_tile<32, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
-    case 64: apply_tile<64, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
-    case 128: apply_tile<128, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
-    case 256: apply_tile<256, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
-    case 512: apply_tile<512, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
-    case 1024: apply_tile<1024, ROLE, T, KIND>(P, A, tile, lds, tw, red); break;
+    GPE_APPLY_CASE(16) GPE_APPLY_CASE(32) GPE_APPLY_CASE(64) GPE_APPLY_CASE(128)
+    GPE_APPLY_CASE(256) GPE_APPLY_CASE(512) GPE_APPLY_CASE(1024)
     default: break;
   }
+#undef GPE_APPLY_CASE
 }
 
 }  // namespace gpe

@@ -224,23 +224,31 @@ __device__ __forceinline__ void dftR(cx<T>* u) {
 }
 
 // ---------------------------------------------------------------------------
-// Line FFT plan: N points handled by TL = N/E threads holding E = 8 values
-// each; thread t holds v[e] = line[t + e*TL] before and after a transform.
-// Radix-8 stages, then one stage of the remaining factor; the inverse runs
-// the stages in reverse order so that the forward output (natural frequency
-// order, register e = frequency t + e*TL) stays in registers across the
-// multiplier.  Twiddles come from a per-workgroup LDS table
-// tw[m] = exp(-2 pi i m / N), m < N.
+// Line FFT plan: N points handled by TL = N/E threads holding E values each
+// (E = 8 or 4); thread t holds v[e] = line[t + e*TL] before and after a
+// transform.  Radix-E stages, then one stage of the remaining factor; the
+// inverse runs the stages in reverse order so that the forward output
+// (natural frequency order, register e = frequency t + e*TL) stays in
+// registers across the multiplier.  Twiddles come from a per-workgroup LDS
+// table tw[m] = exp(-2 pi i m / N), m < N.  E = 4 gives a line twice the
+// threads and each thread half the points: shorter per-thread chains where a
+// pass is latency bound, one more LDS exchange per transform.
 // ---------------------------------------------------------------------------
-template <int N> struct Plan;
-template <> struct Plan<16>   { static constexpr int E = 8, NS = 2; static constexpr int R[2] = {8, 2}; };
-template <> struct Plan<32>   { static constexpr int E = 8, NS = 2; static constexpr int R[2] = {8, 4}; };
-template <> struct Plan<64>   { static constexpr int E = 8, NS = 2; static constexpr int R[2] = {8, 8}; };
-template <> struct Plan<128>  { static constexpr int E = 8, NS = 3; static constexpr int R[3] = {8, 8, 2}; };
-template <> struct Plan<256>  { static constexpr int E = 8, NS = 3; static constexpr int R[3] = {8, 8, 4}; };
-template <> struct Plan<512>  { static constexpr int E = 8, NS = 3; static constexpr int R[3] = {8, 8, 8}; };
-template <> struct Plan<1024> { static constexpr int E = 8, NS = 4; static constexpr int R[4] = {8, 8, 8, 2}; };
-static_assert(Plan<256>::E == kE, "host tiling assumes kE elements per thread");
+template <int N, int E> struct Plan;
+template <> struct Plan<16, 8>   { static constexpr int NS = 2; static constexpr int R[2] = {8, 2}; };
+template <> struct Plan<32, 8>   { static constexpr int NS = 2; static constexpr int R[2] = {8, 4}; };
+template <> struct Plan<64, 8>   { static constexpr int NS = 2; static constexpr int R[2] = {8, 8}; };
+template <> struct Plan<128, 8>  { static constexpr int NS = 3; static constexpr int R[3] = {8, 8, 2}; };
+template <> struct Plan<256, 8>  { static constexpr int NS = 3; static constexpr int R[3] = {8, 8, 4}; };
+template <> struct Plan<512, 8>  { static constexpr int NS = 3; static constexpr int R[3] = {8, 8, 8}; };
+template <> struct Plan<1024, 8> { static constexpr int NS = 4; static constexpr int R[4] = {8, 8, 8, 2}; };
+template <> struct Plan<16, 4>   { static constexpr int NS = 2; static constexpr int R[2] = {4, 4}; };
+template <> struct Plan<32, 4>   { static constexpr int NS = 3; static constexpr int R[3] = {4, 4, 2}; };
+template <> struct Plan<64, 4>   { static constexpr int NS = 3; static constexpr int R[3] = {4, 4, 4}; };
+template <> struct Plan<128, 4>  { static constexpr int NS = 4; static constexpr int R[4] = {4, 4, 4, 2}; };
+template <> struct Plan<256, 4>  { static constexpr int NS = 4; static constexpr int R[4] = {4, 4, 4, 4}; };
+template <> struct Plan<512, 4>  { static constexpr int NS = 5; static constexpr int R[5] = {4, 4, 4, 4, 2}; };
+template <> struct Plan<1024, 4> { static constexpr int NS = 5; static constexpr int R[5] = {4, 4, 4, 4, 4}; };
 
 // LDS addressing of a line element: `lane` is the line inside the tile,
 // `pos` the position on the line.  Contiguous tiles store lines one after
@@ -260,10 +268,9 @@ __host__ __device__ inline int lds_elems(int n, int lanes, bool strided) {
   return strided ? n * (lanes + 1) : lanes * (n + n / 16);
 }
 
-template <int N, int R, bool INV, bool LAST, typename T>
+template <int N, int E, int R, bool INV, bool LAST, typename T>
 __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, int ns, int lane, const LdsMap& mp,
                                                cx<T>* lds, const cx<T>* twl) {
-  constexpr int E = Plan<N>::E;
   constexpr int TL = N / E;
   constexpr int B = E / R;  // butterflies per thread
   cx<T> out[E];
@@ -302,30 +309,30 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, int ns, int lane
   }
 }
 
-template <int N, bool INV, int S, typename T>
+template <int N, int E, bool INV, int S, typename T>
 __device__ __forceinline__ void run_stages(cx<T>* v, int t, int ns, int lane, const LdsMap& mp, cx<T>* lds,
                                            const cx<T>* twl) {
-  using P = Plan<N>;
+  using P = Plan<N, E>;
   if constexpr (S < P::NS) {
     constexpr int R = INV ? P::R[P::NS - 1 - S] : P::R[S];
     constexpr bool LAST = (S == P::NS - 1);
     if constexpr (!LAST) __syncthreads();   // nobody still reads the LDS lines
-    stockham_stage<N, R, INV, LAST>(v, t, ns, lane, mp, lds, twl);
-    run_stages<N, INV, S + 1>(v, t, ns * R, lane, mp, lds, twl);
+    stockham_stage<N, E, R, INV, LAST>(v, t, ns, lane, mp, lds, twl);
+    run_stages<N, E, INV, S + 1>(v, t, ns * R, lane, mp, lds, twl);
   }
 }
 
 // Full line transform; every thread of the workgroup must call it (barriers).
-template <int N, bool INV, typename T>
+template <int N, int E, bool INV, typename T>
 __device__ __forceinline__ void line_fft(cx<T>* v, int t, int lane, const LdsMap& mp, cx<T>* lds,
                                          const cx<T>* twl) {
-  run_stages<N, INV, 0>(v, t, 1, lane, mp, lds, twl);
+  run_stages<N, E, INV, 0>(v, t, 1, lane, mp, lds, twl);
 }
 
 // Per-workgroup twiddle table exp(-2 pi i m / N) from the 1024-entry table.
 // Callers issue it before a barrier that precedes the first stage using it.
-// The workgroup has at least N/8 threads (lanes x N/8), so eight rounds
-// cover the table.  fetch issues the loads, store writes the LDS table;
+// The workgroup has at least N/8 threads (lanes x N/E, E <= 8), so eight
+// rounds cover the table.  fetch issues the loads, store writes the LDS table;
 // callers put their other loads in between so that all go out together.
 template <int N, typename T>
 struct TwiddleFetch {

@@ -29,9 +29,9 @@ __device__ __forceinline__ int role_axis(int role, int dim) {
 // For finite differences position p reads array index p-1 and position 0
 // holds the boundary value 0; positions 1 .. N-1 are inner.
 // `P` is a local copy of the descriptor.
-template <int N>
+template <int N, int EPT>
 struct Tile {
-  static constexpr int E = Plan<N>::E, TL = N / E;
+  static constexpr int E = EPT, TL = N / E;
   int lanes, lane, t, ax;
   int c0, c1, c2;    // array coordinates of the line's first point (x, y, z)
   bool act, sine, fd;
@@ -127,19 +127,19 @@ __device__ __forceinline__ CT axis_mult(int k, int n, CT two_pi_over_len, CT rc,
 // Finite differences (§2.1): -1/2 (u_{p+1} - 2 u_p + u_{p-1}) / h^2 along
 // the line through the LDS line buffer; u at position 0 is the boundary
 // value 0 (the caller's sign factor), the value past position N-1 the other.
-template <int N, typename CT>
-__device__ __forceinline__ void fd_stencil(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
+template <int N, int E, typename CT>
+__device__ __forceinline__ void fd_stencil(const ProbDev& P, int ax, const Tile<N, E>& T, cx<CT>* v,
                                            cx<CT>* lds) {
   cx<CT>* data = lds + N;
   __syncthreads();       // nobody still reads the LDS lines
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
+  for (int e = 0; e < E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
   __syncthreads();
   const double h = pick3(P.h, ax);
   const CT c = (CT)(0.5 / (h * h));
   const cx<CT> zero{(CT)0, (CT)0};
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int p = T.pos(e);
     const cx<CT> lft = data[T.mp.idx(T.lane, p > 0 ? p - 1 : 0, N)];
     const cx<CT> rgt = data[T.mp.idx(T.lane, p < N - 1 ? p + 1 : N - 1, N)];
@@ -165,18 +165,18 @@ __device__ __forceinline__ int* sine_flag_store() {
   __shared__ int f[64];   // lines per tile of a sine pass: at most 256 threads / 4
   return f;
 }
-template <int N, typename CT>
-__device__ __forceinline__ void sine_parity_in(const Tile<N>& T, const cx<CT>* v, cx<CT>* data) {
+template <int N, int E, typename CT>
+__device__ __forceinline__ void sine_parity_in(const Tile<N, E>& T, const cx<CT>* v, cx<CT>* data) {
   constexpr int H = N / 2;
   int* flags = sine_flag_store();
   __syncthreads();       // nobody still reads the LDS lines
   if (T.t == 0) flags[T.lane] = 3;
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
+  for (int e = 0; e < E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
   __syncthreads();
   int bad = 0;
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int p = T.pos(e);
     if (p > 0 && p < H) {
       const cx<CT> q = data[T.mp.idx(T.lane, H - p, N)];
@@ -186,19 +186,19 @@ __device__ __forceinline__ void sine_parity_in(const Tile<N>& T, const cx<CT>* v
   }
   if (bad) atomicAnd(&flags[T.lane], ~bad);
 }
-template <int N, typename CT>
-__device__ __forceinline__ void sine_parity_out(const Tile<N>& T, cx<CT>* v, cx<CT>* data) {
+template <int N, int E, typename CT>
+__device__ __forceinline__ void sine_parity_out(const Tile<N, E>& T, cx<CT>* v, cx<CT>* data) {
   constexpr int H = N / 2;
   const int* flags = sine_flag_store();
   __syncthreads();       // the last transform stage has read its LDS lines
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
+  for (int e = 0; e < E; ++e) data[T.mp.idx(T.lane, T.pos(e), N)] = v[e];
   __syncthreads();
   const int f = flags[T.lane];
   if (f == 0) return;
   const CT half = (CT)0.5;
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int p = T.pos(e);
     if (p > 0 && p < H) {
       const cx<CT> q = data[T.mp.idx(T.lane, H - p, N)];
@@ -211,34 +211,34 @@ __device__ __forceinline__ void sine_parity_out(const Tile<N>& T, cx<CT>* v, cx<
 // (spectral_inverse) of the tile's lines; spectral_apply is both.  `lds`
 // holds the twiddle table (N entries) followed by the line data.  Finite
 // differences apply their stencil in the forward half.
-template <int N, typename CT>
-__device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
+template <int N, int E, typename CT>
+__device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const Tile<N, E>& T, cx<CT>* v,
                                                  cx<CT>* lds) {
   if (T.fd) {
-    fd_stencil<N, CT>(P, ax, T, v, lds);
+    fd_stencil<N, E, CT>(P, ax, T, v, lds);
     return;
   }
-  if (T.sine) sine_parity_in<N, CT>(T, v, lds + N);
-  line_fft<N, false>(v, T.t, T.lane, T.mp, lds + N, lds);
+  if (T.sine) sine_parity_in<N, E, CT>(T, v, lds + N);
+  line_fft<N, E, false>(v, T.t, T.lane, T.mp, lds + N, lds);
   const CT rc = (CT)T.rot(P);
   const CT tpl = (CT)(6.283185307179586477 / pick3(P.len, ax));
   const CT inv_n = (CT)1 / (CT)N;
 #pragma unroll
-  for (int e = 0; e < Tile<N>::E; ++e) {
-    const CT mlt = axis_mult<CT>(T.t + e * Tile<N>::TL, N, tpl, rc, inv_n);
+  for (int e = 0; e < E; ++e) {
+    const CT mlt = axis_mult<CT>(T.t + e * (N / E), N, tpl, rc, inv_n);
     v[e] = mlt * v[e];
   }
 }
-template <int N, typename CT>
-__device__ __forceinline__ void spectral_inverse(const Tile<N>& T, cx<CT>* v, cx<CT>* lds) {
-  if (!T.fd) line_fft<N, true>(v, T.t, T.lane, T.mp, lds + N, lds);
-  if (T.sine) sine_parity_out<N, CT>(T, v, lds + N);
+template <int N, int E, typename CT>
+__device__ __forceinline__ void spectral_inverse(const Tile<N, E>& T, cx<CT>* v, cx<CT>* lds) {
+  if (!T.fd) line_fft<N, E, true>(v, T.t, T.lane, T.mp, lds + N, lds);
+  if (T.sine) sine_parity_out<N, E, CT>(T, v, lds + N);
 }
-template <int N, typename CT>
-__device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N>& T, cx<CT>* v,
+template <int N, int E, typename CT>
+__device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N, E>& T, cx<CT>* v,
                                                cx<CT>* lds) {
-  spectral_forward<N, CT>(P, ax, T, v, lds);
-  spectral_inverse<N, CT>(T, v, lds);
+  spectral_forward<N, E, CT>(P, ax, T, v, lds);
+  spectral_inverse<N, E, CT>(T, v, lds);
 }
 
 // One slot of the fixed-order reduction (the same bits as that slot of the
@@ -485,14 +485,13 @@ struct OOps {
 // pass from one wavefront per SIMD to two, which pays where the launch has
 // enough tiles to be bandwidth bound and costs a little latency where not.
 // ---------------------------------------------------------------------------
-template <int N, int ROLE, typename CT, class Ops, bool RR>
+template <int N, int E, int ROLE, typename CT, class Ops, bool RR>
 __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState& S, int tile, const Ops& ops,
                                             cx<CT>* lds, const cx<CT>* tw1024, double* red) {
-  constexpr int E = Tile<N>::E;
   constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   constexpr bool EPI = (ROLE == R_FINAL || ROLE == R_SOLO);
   const int ax = role_axis(ROLE, P.dim);
-  const Tile<N> T(P, ax, HAS_T, tile);
+  const Tile<N, E> T(P, ax, HAS_T, tile);
   TwiddleFetch<N, CT> twf;
   twf.fetch(tw1024);
   typename Ops::In in[E];
@@ -536,7 +535,7 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
     c = renorm_c(S, bc);
     n_hat = c * c * bc;
   }
-  spectral_apply<N, CT>(P, ax, T, v, lds);
+  spectral_apply<N, E, CT>(P, ax, T, v, lds);
   if constexpr (ROLE == R_FIRST) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -703,20 +702,20 @@ __device__ __forceinline__ void pin_desc_fields(ProbDev& P) {
 }
 
 // Dispatch on the problem's mode.  PREC64: every array float64.
-template <int N, int ROLE, bool PREC64, bool RR>
+template <int N, int E, int ROLE, bool PREC64, bool RR>
 __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverState& S, int tile, char* smem,
                                                 const cx<double>* twd, const cx<float>* twf, double* red) {
   using TS = typename std::conditional<PREC64, double, float>::type;   // F/W storage and transforms
   const cx<TS>* tws = PREC64 ? reinterpret_cast<const cx<TS>*>(twd) : reinterpret_cast<const cx<TS>*>(twf);
   if (S.mode == M_F) {
     FOps<TS> ops(P, S);
-    solver_tile<N, ROLE, TS, FOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
+    solver_tile<N, E, ROLE, TS, FOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_W) {
     WOps<TS> ops(P, S);
-    solver_tile<N, ROLE, TS, WOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
+    solver_tile<N, E, ROLE, TS, WOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_OUTER) {
     OOps<TS, TS> ops(P, S);
-    solver_tile<N, ROLE, double, OOps<TS, TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd,
+    solver_tile<N, E, ROLE, double, OOps<TS, TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd,
                                                    red);
   }
 }
@@ -754,17 +753,21 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
     }
   }
   if (S.mode == M_IDLE) return;
-  const int n = pick3(P.nl, role_axis(ROLE, P.dim));
+  // line length and points per thread of this pass (E = N lanes / threads)
+  const int ax = role_axis(ROLE, P.dim);
+  const int n = pick3(P.nl, ax);
+  const bool e4 = n * pick3(P.lanes, ax) == 4 * (int)blockDim.x;
+#define GPE_SOLVER_CASE(NN)                                                                  \
+  case NN:                                                                                   \
+    if (e4) solver_dispatch<NN, 4, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red);     \
+    else solver_dispatch<NN, 8, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red);        \
+    break;
   switch (n) {
-    case 16: solver_dispatch<16, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
-    case 32: solver_dispatch<32, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
-    case 64: solver_dispatch<64, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
-    case 128: solver_dispatch<128, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
-    case 256: solver_dispatch<256, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
-    case 512: solver_dispatch<512, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
-    case 1024: solver_dispatch<1024, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); break;
+    GPE_SOLVER_CASE(16) GPE_SOLVER_CASE(32) GPE_SOLVER_CASE(64) GPE_SOLVER_CASE(128)
+    GPE_SOLVER_CASE(256) GPE_SOLVER_CASE(512) GPE_SOLVER_CASE(1024)
     default: break;
   }
+#undef GPE_SOLVER_CASE
   if constexpr (ROLE == R_FINAL || ROLE == R_SOLO)
     if (P.step_at == STEP_LAST_GROUP)
       step_if_last(P, st_in + bm.x, ROLE == R_SOLO ? 1 : pick3(P.tiles, P.dim - 1), PREC64 ? 1 : 0, red);

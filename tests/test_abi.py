@@ -71,7 +71,7 @@ def test_host_only_entry_points():
     assert L.gpe_ctx_create(None, 0, None) == nat.GPE_EINVAL
     assert L.gpe_apply_h(None, None, 0, None, None, None) == nat.GPE_EINVAL
     assert L.gpe_solve(None, None, None, None, None) == nat.GPE_EINVAL
-    assert L.gpe_set_plan(None, None, 0, None, 0) == nat.GPE_EINVAL
+    assert L.gpe_set_plan(None, None, 0, None, None, 0) == nat.GPE_EINVAL
     assert L.gpe_hess_vec(None, None, 0, None, None, 0.0, None) == nat.GPE_EINVAL
     assert L.gpe_retract(None, 1, 0, None, None, 0.1, None, None) == nat.GPE_EINVAL
 

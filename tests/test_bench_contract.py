@@ -30,7 +30,9 @@ def test_recorded_plans_are_valid():
         n = [int(v) for v in grid.split("x")]
         assert plan["step_at"] in (0, 1, 2), key
         for a, na in enumerate(n):
-            t, tl = plan["threads"][a], na // 8
+            e = plan.get("elems", [8, 8, 8])[a]
+            assert e in (4, 8), key
+            t, tl = plan["threads"][a], na // e
             assert t in (64, 128, 256) and t >= tl and t % tl == 0, (key, a, t)
 
 

@@ -495,14 +495,17 @@ def test_set_plan(dev):
     from paper_1504_02891_amd.api import GpeError
     p = W.Problem(dim=2, n=(128, 32), lo=(-10.0, -6.0), hi=(10.0, 6.0), beta=300.0, omega=0.2)
     phi0 = W.rotating_initial(p, 0.2, 13)
-    dev.set_plan(p, "fp64", [64, 64, 0], 1)
-    phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="fp64")
-    phi_b, rb = _gpu_solve(dev, p, phi0, tol=1e-8, precision="fp64", threads=[64, 64, 0], step_at="kernel")
-    assert ra["status"] == 0 and ra["nfe"] == rb["nfe"]
-    assert np.array_equal(phi_a, phi_b)
-    for thr, sa in (([32, 64, 0], 1), ([64, 96, 0], 1), ([64, 64, 0], 5), ([64, 64, 0], 3)):
+    for ept in ([8, 8, 0], [4, 4, 0]):
+        dev.set_plan(p, "fp64", [64, 64, 0], 1, elems=ept)
+        phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="fp64")
+        phi_b, rb = _gpu_solve(dev, p, phi0, tol=1e-8, precision="fp64", threads=[64, 64, 0], elems=ept,
+                               step_at="kernel")
+        assert ra["status"] == 0 and ra["nfe"] == rb["nfe"]
+        assert np.array_equal(phi_a, phi_b)
+    for thr, sa, ept in (([32, 64, 0], 1, None), ([64, 96, 0], 1, None), ([64, 64, 0], 5, None),
+                         ([64, 64, 0], 3, None), ([64, 64, 0], 1, [5, 8, 8]), ([64, 64, 0], 1, [8, 2, 8])):
         with pytest.raises(GpeError) as e:
-            dev.set_plan(p, "fp64", thr, sa)
+            dev.set_plan(p, "fp64", thr, sa, elems=ept)
         assert e.value.status == -1
 
 
@@ -514,13 +517,13 @@ def test_autotune_plan(dev):
     plan = dev.autotune(p, "mixed")
     assert plan["us_per_eval"] > 0.0 and plan["step_at"] in (0, 1, 2)
     for a, n in enumerate(p.n):
-        t = plan["threads"][a]
-        assert t in (64, 128, 256) and t % (n // 8) == 0, plan
+        t, e = plan["threads"][a], plan["elems"][a]
+        assert e in (4, 8) and t in (64, 128, 256) and t % (n // e) == 0, plan
     phi0 = W.rotating_initial(p, 0.3, 12)
     # no FP64 continuation: its passes would take the FP64 plan of the grid
     # in one run and the given threads in the other
     phi_a, ra = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed", switch_resid=0.0)
     phi_b, rb = _gpu_solve(dev, p, phi0, tol=1e-8, precision="mixed", threads=plan["threads"][:2] + [0],
-                           step_at=plan["step_at"], switch_resid=0.0)
+                           elems=plan["elems"][:2] + [0], step_at=plan["step_at"], switch_resid=0.0)
     assert ra["status"] == 0 and ra["nfe"] == rb["nfe"]
     assert np.array_equal(phi_a, phi_b)
