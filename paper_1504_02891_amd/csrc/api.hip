@@ -40,7 +40,7 @@ constexpr int64_t kFusedMaxTiles = 512;
 
 // Workspace slots owned by a context (grown on demand, freed at destroy).
 enum WsSlot {
-  WS_PROB = 0, WS_STATE, WS_BMAP0, WS_BMAP1, WS_BMAP2, WS_VAXIS, WS_ARENA,
+  WS_PROB = 0, WS_STATE, WS_BMAP0, WS_BMAP1, WS_BMAP2, WS_BMAP3, WS_BMAP4, WS_BMAP5, WS_VAXIS, WS_ARENA,
   WS_APPLY_T, WS_APPLY_PART, WS_APPLY_OUT, WS_APPLY_RPART, WS_APPLY_PROB, WS_APPLY_VAXIS,
   WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_IMAG, WS_TUNE, WS_COUNT
 };
@@ -449,125 +449,169 @@ void keep_plan(gpe_ctx* c, const gpe_problem& p, const TunedPlan& tp) {
   c->plans.push_back(tp);
 }
 
-// delta0 (optional): per-problem initial regularisation delta (an FP64
-// continuation keeps the delta its mixed-precision run reached)
+// The launch plan (workgroup size and points per thread of each pass, step
+// placement) a solve of `probs` in precision `prec` uses, where the options
+// leave it open: a batch whose problems all share one tuned plan takes it
+// whole; otherwise the sizes of the largest problem with a plan (a batch's
+// slowest problems are usually its largest) when they suit every problem's
+// lines.  `thr`, `ept` in/out (the options' values, 0 = open); `step_at` out
+// (the plan's placement, or the options').
+void pick_plan(const gpe_ctx* c, int count, const gpe_problem* probs, int prec, const gpe_options& o, int* thr,
+               int* ept, int* step_at) {
+  for (int a = 0; a < 3; ++a) {
+    thr[a] = o.threads[a];
+    ept[a] = o.elems[a];
+  }
+  *step_at = o.step_at;
+  const TunedPlan* tp = find_plan(c, probs[0], prec);
+  bool all = tp != nullptr;
+  for (int i = 1; i < count && all; ++i) all = find_plan(c, probs[i], prec) == tp;
+  if (!all) {
+    tp = nullptr;
+    int64_t best = -1;
+    for (int i = 0; i < count; ++i) {
+      const TunedPlan* t = find_plan(c, probs[i], prec);
+      int64_t m = 1;
+      for (int a = 0; a < probs[i].dim; ++a) m *= probs[i].n[a];
+      if (t && m > best) { best = m; tp = t; }
+    }
+    for (int i = 0; i < count && tp; ++i)
+      for (int a = 0; a < probs[i].dim; ++a) {
+        const int tl = (probs[i].bc == GPE_BC_SINE ? 2 * probs[i].n[a] : probs[i].n[a]) / tp->elems[a];
+        if (tl < 1 || tp->threads[a] < tl || tp->threads[a] % tl != 0) tp = nullptr;
+        if (!tp) break;
+      }
+  }
+  if (tp && o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0 && o.elems[0] == 0 && o.elems[1] == 0 &&
+      o.elems[2] == 0)
+    for (int a = 0; a < 3; ++a) {
+      thr[a] = tp->threads[a];
+      ept[a] = tp->elems[a];
+    }
+  if (tp && all && o.step_at == GPE_STEP_AUTO) *step_at = tp->step_at;
+}
+
+// One precision's share of a solve: the launch shape of its passes and the
+// block maps of its unfinished problems.  A mixed-precision solve has an
+// FP32 group, from which problems move to the FP64 group when they hand over
+// (reading: Algorithm 1 at the FP32 floor, Algorithm 2 below switch_resid);
+// the groups run side by side, every evaluation launching each non-empty
+// group's passes, so a problem's FP64 continuation starts at the host check
+// after its hand-over whatever the other problems do.
+struct Group {
+  int prec64 = 1;
+  int thr[3] = {0, 0, 0}, ept[3] = {kE, kE, kE};
+  size_t smem[3] = {0, 0, 0};
+  std::vector<ProbDev> pd;       // each problem's descriptor in this precision
+  std::vector<int2> bm[3];
+  void* dbm[3] = {nullptr, nullptr, nullptr};
+};
+
+// Solve `count` problems (one launch sequence for all): Algorithm 1 or 2 in
+// the options' precision; in mixed precision each problem that hands over
+// continues in FP64 from its iterate (written to its phi buffer and read
+// back as an FP64 initial point, the regularisation delta kept, the rest of
+// its step or Newton-step budget), and its counters add up over both runs.
 int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
-               gpe_result* results, const double* delta0 = nullptr) {
+               gpe_result* results) {
   if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
   CHK(check_options(opts));
-  gpe_options o = *opts;
-  // Tuned plans, where the options leave the launch choices open: a batch
-  // whose problems all share one plan takes it whole; otherwise the
-  // workgroup sizes of the largest problem with a plan (a batch's slowest
-  // problems are usually its largest) when they suit every problem's lines.
-  {
-    const TunedPlan* tp = find_plan(c, probs[0], o.precision);
-    bool all = tp != nullptr;
-    for (int i = 1; i < count && all; ++i) all = find_plan(c, probs[i], o.precision) == tp;
-    if (!all) {
-      tp = nullptr;
-      int64_t best = -1;
-      for (int i = 0; i < count; ++i) {
-        const TunedPlan* t = find_plan(c, probs[i], o.precision);
-        int64_t m = 1;
-        for (int a = 0; a < probs[i].dim; ++a) m *= probs[i].n[a];
-        if (t && m > best) { best = m; tp = t; }
-      }
-      for (int i = 0; i < count && tp; ++i)
-        for (int a = 0; a < probs[i].dim; ++a) {
-          const int tl = (probs[i].bc == GPE_BC_SINE ? 2 * probs[i].n[a] : probs[i].n[a]) / tp->elems[a];
-          if (tl < 1 || tp->threads[a] < tl || tp->threads[a] % tl != 0) tp = nullptr;
-          if (!tp) break;
-        }
-    }
-    if (tp && o.threads[0] == 0 && o.threads[1] == 0 && o.threads[2] == 0 && o.elems[0] == 0 && o.elems[1] == 0 &&
-        o.elems[2] == 0)
-      for (int a = 0; a < 3; ++a) {
-        o.threads[a] = tp->threads[a];
-        o.elems[a] = tp->elems[a];
-      }
-    if (tp && all && o.step_at == GPE_STEP_AUTO) o.step_at = tp->step_at;
+  const gpe_options o = *opts;
+  const bool mixed = o.precision == GPE_PREC_MIXED;
+  const int ng = mixed ? 2 : 1;                  // group 0: the options' precision; group 1: FP64 continuation
+  std::vector<Group> grp(ng);
+  grp[0].prec64 = mixed ? 0 : 1;
+  if (mixed) grp[1].prec64 = 1;
+  int plan_step = o.step_at;
+  for (int gi = 0; gi < ng; ++gi) {
+    int sa;
+    pick_plan(c, count, probs, grp[gi].prec64 ? GPE_PREC_FP64 : GPE_PREC_MIXED, o, grp[gi].thr, grp[gi].ept, &sa);
+    if (gi == 0) plan_step = sa;
   }
-  const int prec64 = o.precision == GPE_PREC_FP64;
-  const size_t es = prec64 ? 16 : 8;       // element size of F / W arrays
-  std::vector<ProbDev> pd(count);
+  std::vector<ProbDev> pd0(count);
   std::vector<double> vaxis((size_t)count * 3 * kMaxN);
   const int dim = probs[0].dim;
   for (int i = 0; i < count; ++i) {
     if (!phis[i]) return GPE_EINVAL;
-    CHK(build_prob(&probs[i], &pd[i], &vaxis[(size_t)i * 3 * kMaxN]));
-    if (pd[i].dim != dim) return GPE_EINVAL;
+    CHK(build_prob(&probs[i], &pd0[i], &vaxis[(size_t)i * 3 * kMaxN]));
+    if (pd0[i].dim != dim) return GPE_EINVAL;
   }
-  // geometry of each pass for each problem: points per thread (8, or 4 for
-  // latency-bound problems by default) and workgroup size
-  std::vector<Geom> geo((size_t)count * 3);
-  size_t smem[3] = {0, 0, 0};
-  int ept[3];
-  for (int ax = 0; ax < 3; ++ax) {
-    ept[ax] = o.elems[ax] ? o.elems[ax] : default_elems(pd);
-    const int th = o.threads[ax];
-    if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
-    for (int i = 0; i < count && th != 0 && ax < dim; ++i)
-      if (th % (pd[i].nl[ax] / ept[ax]) != 0 || pd[i].nl[ax] / ept[ax] > 256) return GPE_EINVAL;
-  }
-  for (int i = 0; i < count; ++i)
-    for (int ax = 0; ax < dim; ++ax) {
-      const int th = o.threads[ax] ? o.threads[ax] : default_threads(pd, dim);
-      Geom g = pass_geom(pd[i], ax, ax > 0, th, 16, ept[ax]);
-      geo[(size_t)i * 3 + ax] = g;
-      pd[i].tiles[ax] = g.tiles;
-      pd[i].lanes[ax] = g.lanes;
-      smem[ax] = std::max(smem[ax], g.smem);
+  // geometry of each pass for each problem and group: points per thread
+  // (8, or 4 for latency-bound problems by default) and workgroup size
+  for (Group& g : grp) {
+    g.pd = pd0;
+    for (int ax = 0; ax < 3; ++ax) {
+      if (g.ept[ax] == 0) g.ept[ax] = default_elems(pd0);
+      const int th = g.thr[ax];
+      if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
+      for (int i = 0; i < count && ax < dim; ++i) {
+        const int tl = pd0[i].nl[ax] / g.ept[ax];
+        if (tl > 256 || (th != 0 && th % tl != 0)) return GPE_EINVAL;
+      }
     }
-  int thr[3] = {0, 0, 0};
-  for (int ax = 0; ax < dim; ++ax) {
-    thr[ax] = geo[ax].threads;
-    for (int i = 1; i < count; ++i)
-      if (geo[(size_t)i * 3 + ax].threads != thr[ax]) return GPE_EUNSUPPORTED;  // one workgroup size per pass
+    for (int ax = 0; ax < dim; ++ax) {
+      int thr_ax = 0;
+      for (int i = 0; i < count; ++i) {
+        const int th = g.thr[ax] ? g.thr[ax] : default_threads(pd0, dim);
+        Geom ge = pass_geom(pd0[i], ax, ax > 0, th, 16, g.ept[ax]);
+        g.pd[i].tiles[ax] = ge.tiles;
+        g.pd[i].lanes[ax] = ge.lanes;
+        g.smem[ax] = std::max(g.smem[ax], ge.smem);
+        if (i == 0) thr_ax = ge.threads;
+        else if (ge.threads != thr_ax) return GPE_EUNSUPPORTED;   // one workgroup size per pass
+      }
+      g.thr[ax] = thr_ax;
+    }
   }
   // placement of the scalar step: in the last workgroup of the final pass
   // while that pass is small (a 1D problem is one workgroup, no fence needed),
   // else a launch of its own (a device-scope fence per workgroup costs more
   // than a launch once there are many workgroups)
-  int step_at = o.step_at;
+  int step_at = plan_step;
   if (step_at < 0) {
     int maxt = 0;
-    for (int i = 0; i < count; ++i) maxt = std::max(maxt, pd[i].tiles[dim - 1]);
+    for (int i = 0; i < count; ++i) maxt = std::max(maxt, grp[0].pd[i].tiles[dim - 1]);
     step_at = (dim == 1 || maxt <= 128) ? STEP_LAST_GROUP : STEP_KERNEL;
   }
   // a 1D problem is one pass of one workgroup: its step ends that pass
   if (dim == 1) step_at = STEP_LAST_GROUP;
-  for (int i = 0; i < count; ++i) pd[i].step_at = step_at;
   const bool fused = step_at == STEP_FUSED;
+  for (Group& g : grp)
+    for (int i = 0; i < count; ++i) {
+      g.pd[i].step_at = step_at;
+      g.pd[i].prec64 = g.prec64;
+    }
   // STEP_FUSED alternates two state arrays and two first-pass partials
   // buffers by evaluation parity; an even chunk leaves the latest state in
   // the first array at every host check
   const int chunk = fused ? (o.chunk + 1) & ~1 : o.chunk;
-  // arena layout
-  std::vector<ProbLayout> lay(count);
+  // arena: every problem's arrays in every group's precision
+  std::vector<ProbLayout> lay((size_t)ng * count);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t r = off;
     off += (bytes + 255) & ~(size_t)255;
     return r;
   };
-  for (int i = 0; i < count; ++i) {
-    const size_t m = (size_t)pd[i].m;
-    ProbLayout& L = lay[i];
-    for (int k = 0; k < 2; ++k) {
-      L.off_xf[k] = take(m * es);
-      L.off_gf[k] = take(m * es);
-      L.off_s[k] = take(m * es);
-      L.off_d[k] = take(m * es);
+  for (int gi = 0; gi < ng; ++gi)
+    for (int i = 0; i < count; ++i) {
+      const ProbDev& d = grp[gi].pd[i];
+      const size_t m = (size_t)d.m, es = grp[gi].prec64 ? 16 : 8;   // element size of the F / W arrays
+      ProbLayout& L = lay[(size_t)gi * count + i];
+      for (int k = 0; k < 2; ++k) {
+        L.off_xf[k] = take(m * es);
+        L.off_gf[k] = take(m * es);
+        L.off_s[k] = take(m * es);
+        L.off_d[k] = take(m * es);
+      }
+      L.off_xk = take(m * 16);
+      L.off_gk = take(m * 16);
+      L.off_t = take(m * 16);
+      L.off_p1 = take((size_t)d.tiles[0] * S1_COUNT * sizeof(double));
+      L.off_p1x = take((size_t)d.tiles[0] * S1_COUNT * sizeof(double));
+      L.off_pf = take((size_t)std::max(d.tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
+      L.off_ticket = take(64);
     }
-    L.off_xk = take(m * 16);
-    L.off_gk = take(m * 16);
-    L.off_t = take(m * 16);
-    L.off_p1 = take((size_t)pd[i].tiles[0] * S1_COUNT * sizeof(double));
-    L.off_p1x = take((size_t)pd[i].tiles[0] * S1_COUNT * sizeof(double));
-    L.off_pf = take((size_t)std::max(pd[i].tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
-    L.off_ticket = take(64);
-  }
   // real arithmetic: forced (Omega = 0 required), or automatic when Omega = 0
   // and every phi0 has a zero imaginary part (one max |Im| reduction each)
   bool no_rotation = true;
@@ -579,14 +623,14 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     std::vector<int> nb(count);
     size_t tot = 0;
     for (int i = 0; i < count; ++i) {
-      nb[i] = (int)std::min<int64_t>((pd[i].m + 255) / 256, 256);
+      nb[i] = (int)std::min<int64_t>((pd0[i].m + 255) / 256, 256);
       tot += nb[i];
     }
     void *part, *hp;
     CHK(ws_get(c, WS_IMAG, tot * sizeof(double), &part));
     size_t at = 0;
     for (int i = 0; i < count; ++i) {
-      launch_max_imag(c->s, nb[i], phis[i], pd[i].m, (double*)part + at);
+      launch_max_imag(c->s, nb[i], phis[i], pd0[i].m, (double*)part + at);
       at += nb[i];
     }
     HIPCHK(hipGetLastError());
@@ -597,64 +641,81 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     for (size_t k = 0; k < tot; ++k) mx = std::max(mx, ((const double*)hp)[k]);
     real = mx == 0.0 ? 1 : 0;
   }
-  for (int i = 0; i < count; ++i) pd[i].real = real;
-  void *arena, *dprob, *dstate, *dvax, *dbm[3] = {nullptr, nullptr, nullptr};
+  void *arena, *dprob, *dstate, *dvax;
   CHK(ws_get(c, WS_ARENA, off, &arena));
   CHK(ws_get(c, WS_PROB, sizeof(ProbDev) * count, &dprob));
   CHK(ws_get(c, WS_STATE, 2 * sizeof(SolverState) * count, &dstate));
   CHK(ws_get(c, WS_VAXIS, vaxis.size() * sizeof(double), &dvax));
   char* A = (char*)arena;
-  for (int i = 0; i < count; ++i) {
-    ProbLayout& L = lay[i];
-    ProbDev& d = pd[i];
-    for (int k = 0; k < 2; ++k) {
-      d.xf[k] = A + L.off_xf[k];
-      d.gf[k] = A + L.off_gf[k];
-      d.s[k] = A + L.off_s[k];
-      d.d[k] = A + L.off_d[k];
+  for (int gi = 0; gi < ng; ++gi)
+    for (int i = 0; i < count; ++i) {
+      const ProbLayout& L = lay[(size_t)gi * count + i];
+      ProbDev& d = grp[gi].pd[i];
+      d.real = real;
+      for (int k = 0; k < 2; ++k) {
+        d.xf[k] = A + L.off_xf[k];
+        d.gf[k] = A + L.off_gf[k];
+        d.s[k] = A + L.off_s[k];
+        d.d[k] = A + L.off_d[k];
+      }
+      d.xk = A + L.off_xk;
+      d.gk = A + L.off_gk;
+      d.t = A + L.off_t;
+      d.part1 = (double*)(A + L.off_p1);
+      d.part1x = (double*)(A + L.off_p1x);
+      d.partF = (double*)(A + L.off_pf);
+      d.ticket = (int32_t*)(A + L.off_ticket);
+      d.v_axis = (const double*)dvax + (size_t)i * 3 * kMaxN;
     }
-    d.xk = A + L.off_xk;
-    d.gk = A + L.off_gk;
-    d.t = A + L.off_t;
-    d.part1 = (double*)(A + L.off_p1);
-    d.part1x = (double*)(A + L.off_p1x);
-    d.partF = (double*)(A + L.off_pf);
-    d.ticket = (int32_t*)(A + L.off_ticket);
-    d.v_axis = (const double*)dvax + (size_t)i * 3 * kMaxN;
-  }
-  // block maps: (problem, tile) for each pass
-  std::vector<int2> bm[3];
-  for (int ax = 0; ax < dim; ++ax)
-    for (int i = 0; i < count; ++i)
-      for (int t = 0; t < pd[i].tiles[ax]; ++t) bm[ax].push_back(make_int2(i, t));
-  for (int ax = 0; ax < dim; ++ax) CHK(ws_get(c, WS_BMAP0 + ax, bm[ax].size() * sizeof(int2), &dbm[ax]));
+  // every problem starts in group 0; the device descriptor array holds each
+  // problem's current one
+  std::vector<int> gof(count, 0);
+  std::vector<ProbDev> cur(count);
+  for (int i = 0; i < count; ++i) cur[i] = grp[0].pd[i];
+  std::vector<char> done_host(count, 0);
+  // block maps of every group: (problem, tile) of its unfinished problems
+  auto build_maps = [&]() {
+    for (int gi = 0; gi < ng; ++gi)
+      for (int ax = 0; ax < dim; ++ax) {
+        grp[gi].bm[ax].clear();
+        for (int i = 0; i < count; ++i)
+          if (gof[i] == gi && !done_host[i])
+            for (int t = 0; t < grp[gi].pd[i].tiles[ax]; ++t) grp[gi].bm[ax].push_back(make_int2(i, t));
+      }
+  };
+  build_maps();
+  for (int gi = 0; gi < ng; ++gi)
+    for (int ax = 0; ax < dim; ++ax) {
+      size_t cap = 0;   // room for every problem of the batch
+      for (int i = 0; i < count; ++i) cap += (size_t)grp[gi].pd[i].tiles[ax];
+      CHK(ws_get(c, WS_BMAP0 + 3 * gi + ax, cap * sizeof(int2), &grp[gi].dbm[ax]));
+    }
   std::vector<SolverState> st(count);
-  for (int i = 0; i < count; ++i) {
-    init_state(st[i], o);
-    if (delta0) st[i].delta = std::min(std::max(delta0[i], o.delta_min), o.delta_max);
-  }
+  for (int i = 0; i < count; ++i) init_state(st[i], o);
   // uploads (staging offsets keep the pieces apart)
   size_t so = 0;
   CHK(upload(c, dvax, vaxis.data(), vaxis.size() * sizeof(double), so));
   so += vaxis.size() * sizeof(double);
-  CHK(upload(c, dprob, pd.data(), sizeof(ProbDev) * count, so));
+  CHK(upload(c, dprob, cur.data(), sizeof(ProbDev) * count, so));
   so += sizeof(ProbDev) * count;
   CHK(upload(c, dstate, st.data(), sizeof(SolverState) * count, so));
   CHK(upload(c, (SolverState*)dstate + count, st.data(), sizeof(SolverState) * count, so));
   so += sizeof(SolverState) * count;
-  for (int ax = 0; ax < dim; ++ax) {
-    CHK(upload(c, dbm[ax], bm[ax].data(), bm[ax].size() * sizeof(int2), so));
-    so += bm[ax].size() * sizeof(int2);
-  }
+  for (int gi = 0; gi < ng; ++gi)
+    for (int ax = 0; ax < dim; ++ax) {
+      const std::vector<int2>& v = grp[gi].bm[ax];
+      if (!v.empty()) CHK(upload(c, grp[gi].dbm[ax], v.data(), v.size() * sizeof(int2), so));
+      so += v.size() * sizeof(int2);
+    }
   const ProbDev* P = (const ProbDev*)dprob;
   SolverState* S = (SolverState*)dstate;
-  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd[i].m, phis[i], prec64);
+  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd0[i].m, phis[i], grp[0].prec64);
   HIPCHK(hipGetLastError());
 
   // profile: an event pair around the last-axis pass of every k-th
-  // evaluation: stamped by the dispatch itself with plain launches, event
-  // record nodes inside a graph (these also count the event packets' own
-  // time, a few microseconds)
+  // evaluation (while one group runs): stamped by the dispatch itself with
+  // plain launches, event record nodes inside a graph (these also count the
+  // event packets' own time, a few microseconds)
   std::vector<hipEvent_t> pev;
   if (o.profile) {
     pev.resize(2 * (size_t)chunk, nullptr);
@@ -662,8 +723,6 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   }
   int64_t eval_index = 0;   // evaluations enqueued so far (profile sampling)
   auto sampled = [&](int64_t e) { return o.profile > 0 && e % o.profile == 0; };
-  // block maps are only needed for batches (workgroup b is tile b of a single problem)
-  auto bmap = [&](int ax) { return count == 1 ? nullptr : (const int2*)dbm[ax]; };
   hipError_t enq_err = hipSuccess;
   // an event record on the stream, or, while capturing, an event-record node
   // appended to the captured graph after the stream's current frontier
@@ -684,32 +743,45 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   bool capturing = false;
   auto enqueue_eval = [&](int k) {
-    // final pass: the epilogue re-reads its inputs once the launch has enough
-    // tiles to be bandwidth bound (four workgroups per compute unit) and the
-    // tiles are two wavefronts or more (measured: 128^3 with 128-thread tiles
-    // 68 -> 49 us per launch; a batch of 64-thread tiles 129 -> 146 us)
-    const int reread = ((int64_t)bm[dim - 1].size() >= kRereadTiles && thr[dim - 1] >= 128) ? 1 : 0;
     const bool prof = sampled(eval_index++);
-    const bool nodes = prof && capturing;                    // event record nodes around the pass
-    hipEvent_t e0 = prof && !capturing ? pev[2 * k] : nullptr, e1 = prof && !capturing ? pev[2 * k + 1] : nullptr;
+    int busy = 0;
+    for (const Group& g : grp) busy += g.bm[dim - 1].empty() ? 0 : 1;
+    const bool timed = prof && busy == 1;
+    const bool nodes = timed && capturing;                   // event record nodes around the pass
+    hipEvent_t e0 = timed && !capturing ? pev[2 * k] : nullptr, e1 = timed && !capturing ? pev[2 * k + 1] : nullptr;
     const int last = dim == 1 ? R_SOLO : R_FINAL;
     // STEP_FUSED: the first pass reads the state of parity `par` and stores
     // the stepped state in the other array, which the later passes read
     const int par = fused ? (k & 1) : 0;
     SolverState* s_in = S + (size_t)par * count;
     SolverState* s_new = fused ? S + (size_t)(par ^ 1) * count : S;
+    // block maps are only needed for batches (workgroup b is tile b of a single problem)
+    auto bmap = [&](const Group& g, int ax) { return count == 1 ? nullptr : (const int2*)g.dbm[ax]; };
     if (dim > 1) {
-      launch_solver_pass(c->s, R_FIRST, prec64, (int)bm[0].size(), thr[0], smem[0], P, s_in, s_new, bmap(0),
-                         c->twd, c->twf, par);
+      for (const Group& g : grp)
+        if (!g.bm[0].empty())
+          launch_solver_pass(c->s, R_FIRST, g.prec64, (int)g.bm[0].size(), g.thr[0], g.smem[0], P, s_in, s_new,
+                             bmap(g, 0), c->twd, c->twf, par);
       if (dim == 3)
-        launch_solver_pass(c->s, R_MID, prec64, (int)bm[1].size(), thr[1], smem[1], P, s_new, s_new, bmap(1),
-                           c->twd, c->twf, par);
+        for (const Group& g : grp)
+          if (!g.bm[1].empty())
+            launch_solver_pass(c->s, R_MID, g.prec64, (int)g.bm[1].size(), g.thr[1], g.smem[1], P, s_new, s_new,
+                               bmap(g, 1), c->twd, c->twf, par);
     }
     if (nodes) record(pev[2 * k]);
-    launch_solver_pass(c->s, last, prec64, (int)bm[dim - 1].size(), thr[dim - 1], smem[dim - 1], P, s_new, s_new,
-                       bmap(dim - 1), c->twd, c->twf, par, e0, e1, reread);
+    for (const Group& g : grp) {
+      if (g.bm[dim - 1].empty()) continue;
+      // final pass: the epilogue re-reads its inputs once the launch has
+      // enough tiles to be bandwidth bound (four workgroups per compute unit)
+      // and the tiles are two wavefronts or more (measured: 128^3 with
+      // 128-thread tiles 68 -> 49 us per launch; a batch of 64-thread tiles
+      // 129 -> 146 us)
+      const int reread = ((int64_t)g.bm[dim - 1].size() >= kRereadTiles && g.thr[dim - 1] >= 128) ? 1 : 0;
+      launch_solver_pass(c->s, last, g.prec64, (int)g.bm[dim - 1].size(), g.thr[dim - 1], g.smem[dim - 1], P,
+                         s_new, s_new, bmap(g, dim - 1), c->twd, c->twf, par, e0, e1, reread);
+    }
     if (nodes) record(pev[2 * k + 1]);
-    if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S, prec64);
+    if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S);
   };
   auto free_events = [&]() {
     for (auto& e : pev)
@@ -718,6 +790,12 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   auto capture = [&]() -> int {
+    if (exec) {
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
     HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
     capturing = true;
     for (int k = 0; k < chunk; ++k) enqueue_eval(k);
@@ -739,41 +817,28 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       return r;
     }
   }
-  // Batches: once the unfinished problems hold at most three quarters of the
-  // launched last-pass tiles, the block maps keep only their tiles and the
-  // chunk is captured again, so that the tail of a batch (its slowest
-  // problems) runs without the finished problems' workgroups.
-  auto compact = [&](const SolverState* hs) -> int {
-    size_t act = 0;
-    for (int i = 0; i < count; ++i)
-      if (!hs[i].done) act += (size_t)pd[i].tiles[dim - 1];
-    if (act == 0 || act * 4 > bm[dim - 1].size() * 3) return GPE_OK;
-    for (int ax = 0; ax < dim; ++ax) {
-      bm[ax].clear();
-      for (int i = 0; i < count; ++i)
-        if (!hs[i].done)
-          for (int t = 0; t < pd[i].tiles[ax]; ++t) bm[ax].push_back(make_int2(i, t));
-    }
-    // staging past the state read-back region; the stream is idle here
-    size_t so2 = (sizeof(SolverState) * count + 255) / 256 * 256;
-    for (int ax = 0; ax < dim; ++ax) {
-      CHK(upload(c, dbm[ax], bm[ax].data(), bm[ax].size() * sizeof(int2), so2));
-      so2 += (bm[ax].size() * sizeof(int2) + 255) / 256 * 256;
-    }
-    if (exec) {
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
-      exec = nullptr;
-      graph = nullptr;
-      CHK(capture());
-    }
+  // new block maps on the device (after a hand-over, or to drop finished
+  // problems' tiles: once a group's unfinished problems hold at most three
+  // quarters of its launched last-pass tiles) and a new graph
+  auto remap = [&](size_t so2) -> int {
+    build_maps();
+    for (int gi = 0; gi < ng; ++gi)
+      for (int ax = 0; ax < dim; ++ax) {
+        const std::vector<int2>& v = grp[gi].bm[ax];
+        if (!v.empty()) CHK(upload(c, grp[gi].dbm[ax], v.data(), v.size() * sizeof(int2), so2));
+        so2 += (v.size() * sizeof(int2) + 255) / 256 * 256;
+      }
+    if (o.use_graph) CHK(capture());
     return GPE_OK;
   };
+  // counters of each problem's finished FP32 run (mixed precision)
+  std::vector<SolverState> first(count);
+  std::vector<char> handed(count, 0);
   double pass_ms = 0.0;
   int64_t pass_n = 0;
   void* pin;
   CHK(pinned_get(c, sizeof(SolverState) * count, &pin));
-  const int64_t cap = eval_cap(o);
+  const int64_t cap = eval_cap(o) * ng;
   int64_t evals = 0;
   int rc = GPE_OK;
   HIPCHK(hipEventRecord(c->t0, c->s));
@@ -793,9 +858,12 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     const SolverState* hs = (const SolverState*)pin;
     bool all = true;
     int64_t maxnfe = 0;
+    std::vector<int> hand;
     for (int i = 0; i < count; ++i) {
-      all = all && hs[i].done;
       maxnfe = std::max<int64_t>(maxnfe, hs[i].nfe);
+      if (hs[i].done && hs[i].status == kStatusStalled && gof[i] == 0 && mixed) hand.push_back(i);
+      else if (hs[i].done) done_host[i] = 1;
+      all = all && done_host[i];
     }
     if (o.profile) {
       // launches of this chunk during which some problem was still active
@@ -811,11 +879,48 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
     if (all) break;
     if (evals > cap) { rc = GPE_NOT_CONVERGED; break; }
-    if (count > 1) {
-      int r = compact(hs);
-      if (r == GPE_OK) r = pinned_get(c, sizeof(SolverState) * count, &pin);   // the staging may have grown
+    // hand-overs: the FP32 iterate goes to the problem's phi buffer, comes
+    // back as the initial point of an FP64 run with the delta it reached and
+    // the rest of its budget
+    size_t so2 = (sizeof(SolverState) * count + 255) / 256 * 256;   // staging past the state read-back
+    std::vector<SolverState> nst;
+    for (int i : hand) {
+      first[i] = hs[i];
+      handed[i] = 1;
+      launch_write_phi(c->s, P, S, i, pd0[i].m, phis[i], 0);
+      gpe_options o2 = o;
+      o2.precision = GPE_PREC_FP64;
+      if (o.algorithm == GPE_ALG1) o2.max_iter = std::max(0, o.max_iter - hs[i].inner_total);
+      else o2.max_outer = std::max(0, o.max_outer - hs[i].outer);
+      SolverState s2;
+      init_state(s2, o2);
+      if (o.algorithm != GPE_ALG1) s2.delta = std::min(std::max(hs[i].delta, o.delta_min), o.delta_max);
+      nst.push_back(s2);
+    }
+    for (size_t k = 0; k < hand.size(); ++k) {
+      const int i = hand[k];
+      gof[i] = 1;
+      cur[i] = grp[1].pd[i];
+      CHK(upload(c, (ProbDev*)dprob + i, &cur[i], sizeof(ProbDev), so2));
+      so2 += (sizeof(ProbDev) + 255) / 256 * 256;
+      CHK(upload(c, S + i, &nst[k], sizeof(SolverState), so2));
+      CHK(upload(c, S + count + i, &nst[k], sizeof(SolverState), so2));
+      so2 += (sizeof(SolverState) + 255) / 256 * 256;
+      launch_init(c->s, P, i, pd0[i].m, phis[i], 1);
+    }
+    HIPCHK(hipGetLastError());
+    bool rebuild = !hand.empty();
+    for (int gi = 0; gi < ng && !rebuild; ++gi) {
+      size_t act = 0;
+      for (int i = 0; i < count; ++i)
+        if (gof[i] == gi && !done_host[i]) act += (size_t)grp[gi].pd[i].tiles[dim - 1];
+      rebuild = count > 1 && act * 4 <= grp[gi].bm[dim - 1].size() * 3;
+    }
+    if (rebuild) {
+      const int r = remap(so2);
       if (r != GPE_OK) { rc = r; break; }
     }
+    if (pinned_get(c, sizeof(SolverState) * count, &pin) != GPE_OK) { rc = GPE_ENOMEM; break; }   // may have grown
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
@@ -827,7 +932,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   if (rc < 0) return rc;
   HIPCHK(hipEventRecord(c->t1, c->s));
   std::memcpy(st.data(), pin, sizeof(SolverState) * count);
-  for (int i = 0; i < count; ++i) launch_write_phi(c->s, P, S, i, pd[i].m, phis[i], prec64);
+  for (int i = 0; i < count; ++i) launch_write_phi(c->s, P, S, i, pd0[i].m, phis[i], grp[gof[i]].prec64);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   float ms = 0.0f;
@@ -838,6 +943,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     std::memset(&r, 0, sizeof(r));
     const SolverState& s = st[i];
     r.status = s.done ? s.status : GPE_NOT_CONVERGED;
+    // a run still in its FP32 phase at the cap, or stopped there, counts its
+    // evaluations as mixed; a handed-over problem adds its FP32 run's
+    const bool in32 = mixed && gof[i] == 0;
     r.outer_iters = s.outer;
     r.inner_iters = s.inner_total;
     r.nfe = s.nfe;
@@ -851,17 +959,34 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     r.nfe_outer = s.nfe_o;
     r.pass_launches = (int32_t)pass_n;
     r.pass_ms = pass_ms;
-    if (!prec64) {
+    if (in32) {
       r.nfe_mixed[0] = s.nfe_f;
       r.nfe_mixed[1] = s.nfe_w;
       r.nfe_mixed[2] = s.nfe_o;
     }
+    if (handed[i]) {
+      const SolverState& a = first[i];
+      r.switch_iter = std::max(1, a.inner_total);
+      r.outer_iters += a.outer;
+      r.inner_iters += a.inner_total;
+      r.nfe += a.nfe;
+      r.nfe_fp64 += a.nfe64;
+      r.backtracks += a.backtracks;
+      r.rejections += a.rejections;
+      r.nfe_f += a.nfe_f;
+      r.nfe_w += a.nfe_w;
+      r.nfe_outer += a.nfe_o;
+      r.nfe_mixed[0] = a.nfe_f;
+      r.nfe_mixed[1] = a.nfe_w;
+      r.nfe_mixed[2] = a.nfe_o;
+    }
+    if (r.status == kStatusStalled) r.status = GPE_NOT_CONVERGED;   // stopped before its continuation ran
     if (r.status >= 0) {
       // outputs recomputed in float64 from the returned phi
       double sc[10];
       ApplyArgs a{0, 0.0, phis[i], nullptr, nullptr};
       void* hout;
-      CHK(ws_get(c, WS_SCRATCH_OUT, (size_t)pd[i].m * 16, &hout));
+      CHK(ws_get(c, WS_SCRATCH_OUT, (size_t)pd0[i].m * 16, &hout));
       a.out = hout;
       CHK(run_apply(c, &probs[i], 1, a, sc));
       r.energy = sc[0];
@@ -880,74 +1005,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   return worst;
 }
 
-// Solve, then continue in FP64 the problems whose mixed-precision run handed
-// over (internal status kStatusStalled: Algorithm 1 at the FP32 floor, or
-// Algorithm 2 at the handover residual): the iterate each left in its phi
-// buffer starts an FP64 run of the same algorithm with the remaining step
-// (Algorithm 1) or Newton-step (Algorithm 2) budget.  Counters add up; the
-// outputs are the FP64 run's.
-int solve_switch(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
-                 gpe_result* results) {
-  int rc = solve_impl(c, count, probs, opts, phis, results);
-  if (rc < 0) return rc;
-  std::vector<int> idx;
-  for (int i = 0; i < count; ++i)
-    if (results[i].status == kStatusStalled) idx.push_back(i);
-  if (idx.empty()) return rc;
-  std::vector<gpe_problem> sp;
-  std::vector<void*> sphi;
-  std::vector<double> d0;
-  int used = 0, used_outer = 0;
-  for (int i : idx) {
-    sp.push_back(probs[i]);
-    sphi.push_back(phis[i]);
-    d0.push_back(results[i].delta);
-    used = std::max(used, results[i].inner_iters);
-    used_outer = std::max(used_outer, results[i].outer_iters);
-  }
-  gpe_options o2 = *opts;
-  o2.precision = GPE_PREC_FP64;
-  if (opts->algorithm == GPE_ALG1) o2.max_iter = std::max(0, opts->max_iter - used);
-  else o2.max_outer = std::max(0, opts->max_outer - used_outer);
-  std::vector<gpe_result> r2(idx.size());
-  const int rc2 = solve_impl(c, (int)idx.size(), sp.data(), &o2, sphi.data(), r2.data(),
-                             opts->algorithm == GPE_ALG1 ? nullptr : d0.data());
-  if (rc2 < 0) {
-    // the handed-over problems carry the continuation's error, not the
-    // internal hand-over status
-    for (int i : idx) results[i].status = rc2;
-    return rc2;
-  }
-  for (size_t k = 0; k < idx.size(); ++k) {
-    gpe_result& a = results[idx[k]];
-    gpe_result b = r2[k];
-    b.switch_iter = std::max(1, a.inner_iters);
-    b.outer_iters += a.outer_iters;
-    b.inner_iters += a.inner_iters;
-    b.nfe += a.nfe;
-    b.nfe_fp64 += a.nfe_fp64;
-    b.backtracks += a.backtracks;
-    b.rejections += a.rejections;
-    b.nfe_f += a.nfe_f;
-    b.nfe_w += a.nfe_w;
-    b.nfe_outer += a.nfe_outer;
-    b.time_ms += a.time_ms;
-    b.pass_launches += a.pass_launches;
-    b.pass_ms += a.pass_ms;
-    for (int k = 0; k < 3; ++k) b.nfe_mixed[k] += a.nfe_mixed[k];
-    a = b;
-  }
-  int worst = GPE_OK;
-  for (int i = 0; i < count; ++i) {
-    if (results[i].status < 0 && worst >= 0) worst = results[i].status;
-    else if (results[i].status == GPE_NOT_CONVERGED && worst == GPE_OK) worst = GPE_NOT_CONVERGED;
-  }
-  return worst;
-}
-
 // Statuses a caller may see: GPE_OK, GPE_NOT_CONVERGED or a documented
 // negative code.  The internal hand-over status never leaves the library
-// (solve_switch replaces it); anything else unexpected reads as not
+// (the solver's FP64 continuation replaces it); anything else unexpected reads as not
 // converged.
 int public_status(int st) {
   if (st == GPE_OK || st == GPE_NOT_CONVERGED) return st;
@@ -958,7 +1018,7 @@ int public_status(int st) {
 int solve_public(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
                  gpe_result* results) {
   if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
-  const int rc = solve_switch(c, count, probs, opts, phis, results);
+  const int rc = solve_impl(c, count, probs, opts, phis, results);
   for (int i = 0; i < count; ++i) results[i].status = public_status(results[i].status);
   return public_status(rc);
 }

@@ -17,7 +17,8 @@ void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int th
                         int reread = 0);
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
-void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64);
+// the scalar step of every problem (its precision from its descriptor)
+void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st);
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64);
 void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
                       int prec64);

@@ -11,11 +11,11 @@ namespace gpe {
 // written back whole.
 constexpr int kStepThreads = 512;
 __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict__ probs,
-                                                       SolverState* __restrict__ states, int prec64) {
+                                                       SolverState* __restrict__ states) {
   __shared__ double red[S1_COUNT + SF_COUNT];
   ProbDev P = probs[blockIdx.x];
   pin_reg(P.part1); pin_reg(P.partF); pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
-  pin_reg(P.dim); pin_reg(P.sqrt_hvol);
+  pin_reg(P.dim); pin_reg(P.sqrt_hvol); pin_reg(P.prec64);
   // the partial sums are reduced before the state is known to need them, so
   // that their loads go out with the state's
   if (threadIdx.x < 64) touch_lines(states + blockIdx.x);
@@ -24,7 +24,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict
   if (states[blockIdx.x].mode == M_IDLE) return;
   if (threadIdx.x == 0) {
     SolverState L = states[blockIdx.x];
-    step_logic(P, L, r1, rf, prec64);
+    step_logic(P, L, r1, rf, P.prec64);
     states[blockIdx.x] = L;
   }
 }
@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(256) k_prolong_axis(const cx<double>* __restri
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, int prec64) {
-  hipLaunchKernelGGL(k_step, dim3(nprob), dim3(kStepThreads), 0, s, probs, st, prec64);
+void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st) {
+  hipLaunchKernelGGL(k_step, dim3(nprob), dim3(kStepThreads), 0, s, probs, st);
 }
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64) {
   const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);

@@ -12,7 +12,10 @@ to far better than 1e-9 relative).  Written next to this script:
 
     fullsize_<name>.json      E, mu, residual, rms, max|phi|^2, evaluation
                               counts of both stages, the key below
-    fullsize_<name>_phi.npz   the polished phi (complex128, x fastest)
+    fullsize_<name>_phi.npz   the polished phi (complex128, x fastest): every
+                              point for the 2D grid; for the 3D grid (Omega = 0,
+                              a real state) its real part at every SAMPLE_3D-th
+                              point of each axis, to keep the file small
 
 The key is a SHA-256 of the problem parameters, the seed recipe and the
 method's constants, so a test can tell when a reference is stale.
@@ -42,6 +45,7 @@ from oracle.unified import UnifiedProblem  # noqa: E402
 
 RAW_TOL = 1e-6
 POLISH_TOL = 1e-8
+SAMPLE_3D = 8
 
 WORKLOADS = {
     "rot2d": ("workloads.rotating_2d()", W.rotating_2d),
@@ -85,7 +89,13 @@ def run(name):
            "raw_log_every_50": [list(r) for r in raw.log[::50]]}
     with open(os.path.join(HERE, f"fullsize_{name}.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
-    np.savez_compressed(os.path.join(HERE, f"fullsize_{name}_phi.npz"), phi=up.to_phi(pol.x))
+    save_phi(name, p, up.to_phi(pol.x))
+
+
+def save_phi(name, p, phi):
+    if p.dim == 3:
+        phi = np.ascontiguousarray(phi[::SAMPLE_3D, ::SAMPLE_3D, ::SAMPLE_3D].real)
+    np.savez_compressed(os.path.join(HERE, f"fullsize_{name}_phi.npz"), phi=phi, sample=SAMPLE_3D if p.dim == 3 else 1)
 
 
 if __name__ == "__main__":
