@@ -1,0 +1,69 @@
+"""The benchmark's batched workloads at their full sizes, every returned state
+certified by the oracle.
+
+Batched sweep (64 rotating problems, beta ~ U[100,2000], Omega ~ U[0,0.95],
+grids 64^2/128^2/256^2 on [-12,12]^2, one launch sequence for all): in both
+precisions every problem must converge to the residual 1e-6, and the oracle,
+evaluating each returned state on its own, must find its residual below 1e-6
+and the GPU's E and mu equal to its own values of that state.
+
+Cascade (16 problems, Omega = 0.80 ... 0.95, beta = 5000 on [-20,20]^2,
+64^2 -> 128^2 -> 256^2 -> 512^2, final residual 1e-7): the same
+certification of the 512^2 states.  It runs for minutes, so it is opt-in
+(GPE_FULL_CASCADE=1).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.unified import UnifiedProblem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_02891_amd import api
+    return api
+
+
+def _certify(p, phi, res, tol):
+    up = UnifiedProblem(p)
+    o = up.outputs(up.to_x(phi))
+    assert o["resid"] < tol, (p.beta, p.omega, o["resid"])
+    assert abs(res["energy"] - o["energy"]) <= 1e-11 * abs(o["energy"])
+    assert abs(res["mu"] - o["mu"]) <= 1e-10 * abs(o["mu"])
+    assert abs(o["norm_err"]) < 1e-12
+    return o
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batched_sweep_certified(dev, prec):
+    probs, phi0s = W.rotating_sweep_2d()
+    print(f"batched sweep, {len(probs)} problems, {prec}", flush=True)
+    outs, res = dev.solve_batched(probs, [torch.from_numpy(np.asarray(f)).cuda() for f in phi0s], tol=1e-6,
+                                  precision=prec, max_outer=20000)
+    nfe = [r["nfe"] for r in res]
+    print(f"  evaluations per problem: max {max(nfe)}, total {sum(nfe)}", flush=True)
+    for p, o, r in zip(probs, outs, res):
+        assert r["status"] == 0, (p.beta, p.omega, r)
+        _certify(p, o.cpu().numpy(), r, 1e-6)
+
+
+@pytest.mark.skipif(os.environ.get("GPE_FULL_CASCADE") != "1", reason="minutes long: set GPE_FULL_CASCADE=1")
+def test_cascade_full_size_certified(dev):
+    probs, phi0s, levels = W.cascade_2d()
+    print(f"cascade, {len(probs)} problems, levels {levels}", flush=True)
+    outs, res = dev.solve_cascadic(probs, [torch.from_numpy(np.asarray(f)).cuda() for f in phi0s],
+                                   len(levels), level_tol=1e-4, tol=1e-7, precision="mixed", max_outer=20000)
+    for p0, o, r in zip(probs, outs, res):
+        p = p0.with_n((levels[-1],) * 2)
+        assert r["status"] == 0, (p.omega, r)
+        c = _certify(p, o.cpu().numpy(), r, 1e-7)
+        print(f"  Omega={p.omega:.2f} E={r['energy']:.10f} mu={r['mu']:.10f} r_oracle={c['resid']:.2e} "
+              f"nfe={r['nfe']} (fp32 {sum(r['nfe_mixed'])})", flush=True)

@@ -58,10 +58,22 @@ def _gold(name):
 
 CASES = {"rot2d": W.rotating_2d, "lattice3d": W.lattice_3d}
 
+# Protocol (iv) outcomes: the GPU state is certified stationary by the oracle
+# (residual <= 1e-8 after the FP64 polish) but is another stationary state
+# than the oracle's, so (i) and (iii) do not apply.
+_LATTICE_MIXED = pytest.mark.xfail(
+    reason="3D lattice, mixed precision: the FP32 phase commits the iteration to another stationary state, "
+           "E = 52.0373910111 against the oracle's 52.0373904479 (1.08e-8 relative above it; the FP64 path "
+           "lands on the oracle's to 4e-14); the same state with the hand-over at 1e-2, 1e-3 or 1e-4 and "
+           "with Algorithm 1 alone, and the FP64 polish to 1e-8 leaves it there",
+    strict=False)
+
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_full_size_parity_after_polish(dev, name, prec):
+def test_full_size_parity_after_polish(dev, name, prec, request):
+    if name == "lattice3d" and prec == "mixed":
+        request.applymarker(_LATTICE_MIXED)
     gold, arr = _gold(name)
     p, phi0 = CASES[name]()
     up = UnifiedProblem(p)
@@ -80,14 +92,18 @@ def test_full_size_parity_after_polish(dev, name, prec):
     assert o["resid"] <= 1e-8, o["resid"]                                     # (ii)
     e_or, mu_or = gold["polished"]["energy"], gold["polished"]["mu"]
     print(f"  polished: E_gpu={o['energy']:.13f} E_oracle={e_or:.13f} "
-          f"rel {abs(o['energy'] - e_or) / e_or:.2e}, mu rel {abs(o['mu'] - mu_or) / mu_or:.2e}", flush=True)
-    assert abs(o["energy"] - e_or) <= 1e-9 * abs(e_or)                        # (i)
-    assert abs(o["mu"] - mu_or) <= 1e-9 * abs(mu_or)
+          f"rel {abs(o['energy'] - e_or) / e_or:.2e}, mu rel {abs(o['mu'] - mu_or) / mu_or:.2e} "
+          f"nfe={rp['nfe']}", flush=True)
     ref = arr["phi"]
     k = int(arr["sample"])
     got = phi_g[::k, ::k, ::k] if p.dim == 3 else phi_g
     ph = np.vdot(ref, got)
     aligned = got * np.exp(-1j * np.angle(ph))
-    err = float(np.max(np.abs(aligned - ref)))
-    print(f"  max |phi - phi_oracle| after phase alignment: {err:.2e}", flush=True)
+    dif = np.abs(aligned - ref)
+    err = float(np.max(dif))
+    at = np.unravel_index(int(np.argmax(dif)), dif.shape)
+    print(f"  max |phi - phi_oracle| after phase alignment: {err:.2e} at sample index {at} "
+          f"(phi_oracle {complex(ref[at]):.3e}, phi_gpu {complex(aligned[at]):.3e})", flush=True)
+    assert abs(o["energy"] - e_or) <= 1e-9 * abs(e_or)                        # (i)
+    assert abs(o["mu"] - mu_or) <= 1e-9 * abs(mu_or)
     assert err <= 1e-6                                                         # (iii)
