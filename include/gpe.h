@@ -24,6 +24,9 @@
  *  - All device work is ordered on the context's stream (gpe_ctx_create).
  *  - Errors are status codes; no C++ exception crosses this interface.  A
  *    context must not be used from two threads at once.
+ *  - Environment: GPE_PROGRESS=<seconds> makes the solvers print a progress
+ *    line on stderr (evaluations so far, problems finished) at host checks at
+ *    least that many seconds apart.
  */
 #ifndef GPE_H
 #define GPE_H

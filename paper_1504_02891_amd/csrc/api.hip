@@ -1,8 +1,10 @@
 // C ABI of the ground-state library: context, workspace, validation, launch
 // geometry and the host loop that replays chunks of solver evaluations.
 #include <hip/hip_runtime.h>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -841,6 +843,11 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   const int64_t cap = eval_cap(o) * ng;
   int64_t evals = 0;
   int rc = GPE_OK;
+  // GPE_PROGRESS=<seconds>: a line on stderr at host checks at least that
+  // far apart (evaluations so far, problems finished), for long solves
+  const char* prog_env = std::getenv("GPE_PROGRESS");
+  const double prog_every = prog_env ? std::atof(prog_env) : 0.0;
+  auto prog_last = std::chrono::steady_clock::now();
   HIPCHK(hipEventRecord(c->t0, c->s));
   for (;;) {
     if (exec) {
@@ -875,6 +882,16 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
           pass_ms += e;
           ++pass_n;
         }
+      }
+    }
+    if (prog_every > 0.0) {
+      const auto now = std::chrono::steady_clock::now();
+      if (std::chrono::duration<double>(now - prog_last).count() >= prog_every) {
+        int fin = 0;
+        for (int i = 0; i < count; ++i) fin += done_host[i] ? 1 : 0;
+        std::fprintf(stderr, "gpe: %lld evaluations, %d of %d problems finished\n", (long long)evals, fin, count);
+        std::fflush(stderr);
+        prog_last = now;
       }
     }
     if (all) break;
