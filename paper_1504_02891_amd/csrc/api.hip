@@ -763,12 +763,12 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       for (const Group& g : grp)
         if (!g.bm[0].empty())
           launch_solver_pass(c->s, R_FIRST, g.prec64, (int)g.bm[0].size(), g.thr[0], g.smem[0], P, s_in, s_new,
-                             bmap(g, 0), c->twd, c->twf, par);
+                             bmap(g, 0), c->twd, c->twf, par, nullptr, nullptr, 0, fused ? 1 : 0, g.ept[0]);
       if (dim == 3)
         for (const Group& g : grp)
           if (!g.bm[1].empty())
             launch_solver_pass(c->s, R_MID, g.prec64, (int)g.bm[1].size(), g.thr[1], g.smem[1], P, s_new, s_new,
-                               bmap(g, 1), c->twd, c->twf, par);
+                               bmap(g, 1), c->twd, c->twf, par, nullptr, nullptr, 0, 0, g.ept[1]);
     }
     if (nodes) record(pev[2 * k]);
     for (const Group& g : grp) {
@@ -780,7 +780,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       // 129 -> 146 us)
       const int reread = ((int64_t)g.bm[dim - 1].size() >= kRereadTiles && g.thr[dim - 1] >= 128) ? 1 : 0;
       launch_solver_pass(c->s, last, g.prec64, (int)g.bm[dim - 1].size(), g.thr[dim - 1], g.smem[dim - 1], P,
-                         s_new, s_new, bmap(g, dim - 1), c->twd, c->twf, par, e0, e1, reread);
+                         s_new, s_new, bmap(g, dim - 1), c->twd, c->twf, par, e0, e1, reread, 0, g.ept[dim - 1]);
     }
     if (nodes) record(pev[2 * k + 1]);
     if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S);

@@ -109,14 +109,12 @@ __global__ void __launch_bounds__(256) k_apply_pass(const ProbDev* __restrict__ 
   __shared__ double red[SA_COUNT * 16];
   const ProbDev P = probs[0];     // local copy: one batch of loads
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  const int ax = role_axis(ROLE, P.dim);
-  const int n = pick3(P.nl, ax);
-  const bool e4 = n * pick3(P.lanes, ax) == 4 * (int)blockDim.x;    // points per thread 4 or 8
+  // the stand-alone passes take kE (8) points per thread
+  const int n = pick3(P.nl, role_axis(ROLE, P.dim));
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
 #define GPE_APPLY_CASE(NN)                                                      \
   case NN:                                                                      \
-    if (e4) apply_tile<NN, 4, ROLE, T, KIND>(P, A, tile, lds, tw, red);         \
-    else apply_tile<NN, 8, ROLE, T, KIND>(P, A, tile, lds, tw, red);            \
+    apply_tile<NN, kE, ROLE, T, KIND>(P, A, tile, lds, tw, red);                \
     break;
   switch (n) {
     GPE_APPLY_CASE(16) GPE_APPLY_CASE(32) GPE_APPLY_CASE(64) GPE_APPLY_CASE(128)

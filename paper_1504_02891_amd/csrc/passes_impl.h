@@ -721,12 +721,17 @@ __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverSt
 }
 
 // `bmap` maps a workgroup to (problem, tile); null for a single problem
-// (workgroup b is tile b of problem 0).  RR: see solver_tile.  The passes
+// (workgroup b is tile b of problem 0).  EPT: transform points per thread
+// (8 or 4; the host launches the instance of its plan).  RR: see
+// solver_tile.  FUSED (first
+// pass only): the pass runs the previous evaluation's scalar step first
+// (STEP_FUSED; an instance of its own, so that the other instances carry
+// none of its code and registers).  The passes
 // read the state from st_in; with STEP_FUSED the first pass stores the state
 // after its step in st_out (the host alternates two state arrays and passes
 // the evaluation's parity `par`, which also selects the first-pass partials
 // buffer); otherwise st_out is st_in and par is 0.
-template <int ROLE, bool PREC64, bool RR>
+template <int ROLE, bool PREC64, bool RR, bool FUSED, int EPT>
 __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__ probs,
                                                      SolverState* __restrict__ st_in,
                                                      SolverState* __restrict__ st_out,
@@ -745,22 +750,16 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   GPE_PASS_STATE_FIELDS(pin_reg);
   double* const part1_other = par ? P.part1 : P.part1x;
   if (par) P.part1 = P.part1x;
-  if constexpr (ROLE == R_FIRST) {
-    if (P.step_at == STEP_FUSED) {
-      fused_step(P, S, part1_other, st_out + bm.x, bm.y == 0, PREC64 ? 1 : 0);
-      GPE_PASS_STATE_FIELDS(make_uniform);
-      GPE_PASS_STATE_FIELDS(pin_reg);
-    }
+  if constexpr (ROLE == R_FIRST && FUSED) {
+    fused_step(P, S, part1_other, st_out + bm.x, bm.y == 0, PREC64 ? 1 : 0);
+    GPE_PASS_STATE_FIELDS(make_uniform);
   }
   if (S.mode == M_IDLE) return;
-  // line length and points per thread of this pass (E = N lanes / threads)
-  const int ax = role_axis(ROLE, P.dim);
-  const int n = pick3(P.nl, ax);
-  const bool e4 = n * pick3(P.lanes, ax) == 4 * (int)blockDim.x;
-#define GPE_SOLVER_CASE(NN)                                                                  \
-  case NN:                                                                                   \
-    if (e4) solver_dispatch<NN, 4, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red);     \
-    else solver_dispatch<NN, 8, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red);        \
+  // line length of this pass; EPT points per thread (an instance per count)
+  const int n = pick3(P.nl, role_axis(ROLE, P.dim));
+#define GPE_SOLVER_CASE(NN)                                                   \
+  case NN:                                                                    \
+    solver_dispatch<NN, EPT, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); \
     break;
   switch (n) {
     GPE_SOLVER_CASE(16) GPE_SOLVER_CASE(32) GPE_SOLVER_CASE(64) GPE_SOLVER_CASE(128)
