@@ -345,15 +345,22 @@ int gpe_prolong(gpe_ctx* ctx, const gpe_problem* coarse, const gpe_problem* fine
 
 /*
  * Algorithm 3: cascadic multigrid over `nlevels` grids (n doubling per
- * level, coarse problem given), each level solved by gpe_solve_batched for
- * all `count` problems, coarse levels to `level_tol`, the finest to opts->tol.
- * phi0s[i]: DEVICE complex128 initial data on the coarse grid (read only);
- * phis[i]: DEVICE complex128 outputs on the finest grid.  Fourier problems only.
- * results[i]: the finest level's outputs (E, mu, residual, ...); every counter
- * (iterations, evaluations by kind and precision, backtracks, rejections,
- * switch_iter, profile samples, time) summed over the levels; the status is
- * the worst of the levels' (a coarse level stopped at its cap reports
- * GPE_NOT_CONVERGED).
+ * level, coarse problem given) for `count` problems in one solve: coarse
+ * levels to `level_tol`, the finest to opts->tol.  Each problem moves on by
+ * itself: when it ends a coarse level its iterate is prolonged (as
+ * gpe_prolong) and starts the next level's solve, in the options' precision
+ * with a fresh step state, at the solver's next host check, while the other
+ * problems continue on their own levels (in mixed precision a level's FP64
+ * continuation runs the same way).  phi0s[i]: DEVICE complex128 initial data
+ * on the coarse grid, read at the start only; phis[i]: DEVICE complex128
+ * outputs on the finest grid, also the write-back space of the coarse levels.
+ * Fourier problems only.  results[i]: the finest level's outputs (E, mu,
+ * residual, ...); every counter (iterations, evaluations by kind and
+ * precision, backtracks, rejections, switch_iter) summed over the levels;
+ * profile samples and time are the whole solve's.  The status is the worst
+ * of the levels' (a coarse level stopped at its cap reports
+ * GPE_NOT_CONVERGED); a problem the evaluation cap stops on a coarse level
+ * returns its iterate prolonged to the finest grid and GPE_NOT_CONVERGED.
  */
 int gpe_solve_cascadic(gpe_ctx* ctx, int32_t count, const gpe_problem* coarse,
                        int32_t nlevels, double level_tol, const gpe_options* opts,

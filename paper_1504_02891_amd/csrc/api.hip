@@ -42,9 +42,9 @@ constexpr int64_t kFusedMaxTiles = 512;
 
 // Workspace slots owned by a context (grown on demand, freed at destroy).
 enum WsSlot {
-  WS_PROB = 0, WS_STATE, WS_BMAP0, WS_BMAP1, WS_BMAP2, WS_BMAP3, WS_BMAP4, WS_BMAP5, WS_VAXIS, WS_ARENA,
+  WS_PROB = 0, WS_STATE, WS_BMAP, WS_VAXIS, WS_ARENA,
   WS_APPLY_T, WS_APPLY_PART, WS_APPLY_OUT, WS_APPLY_RPART, WS_APPLY_PROB, WS_APPLY_VAXIS,
-  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_LEVEL1, WS_IMAG, WS_TUNE, WS_COUNT
+  WS_SCRATCH_OUT, WS_RETRACT, WS_PROLONG0, WS_PROLONG1, WS_LEVEL0, WS_IMAG, WS_TUNE, WS_COUNT
 };
 
 }  // namespace
@@ -493,6 +493,26 @@ void pick_plan(const gpe_ctx* c, int count, const gpe_problem* probs, int prec, 
   if (tp && all && o.step_at == GPE_STEP_AUTO) *step_at = tp->step_at;
 }
 
+// Trigonometric prolongation (Algorithm 3) of the complex128 grid function
+// `src` of problem `dc` to the grid with every n doubled, axis by axis (the
+// intermediate shapes in the context's prolongation buffers), into `dst`.
+int enqueue_prolong(gpe_ctx* c, const ProbDev& dc, const void* src, void* dst) {
+  int n[3] = {dc.n[0], dc.n[1], dc.n[2]};
+  for (int ax = 0; ax < dc.dim; ++ax) {
+    void* out = dst;
+    if (ax < dc.dim - 1) {
+      int nn[3] = {n[0], n[1], n[2]};
+      nn[ax] *= 2;
+      CHK(ws_get(c, ax == 0 ? WS_PROLONG0 : WS_PROLONG1, (size_t)nn[0] * nn[1] * nn[2] * 16, &out));
+    }
+    if (launch_prolong_axis(c->s, src, out, n[0], n[1], n[2], ax, c->twd) != 0) return GPE_EUNSUPPORTED;
+    HIPCHK(hipGetLastError());
+    n[ax] *= 2;
+    src = out;
+  }
+  return GPE_OK;
+}
+
 // One precision's share of a solve: the launch shape of its passes and the
 // block maps of its unfinished problems.  A mixed-precision solve has an
 // FP32 group, from which problems move to the FP64 group when they hand over
@@ -502,6 +522,7 @@ void pick_plan(const gpe_ctx* c, int count, const gpe_problem* probs, int prec, 
 // after its hand-over whatever the other problems do.
 struct Group {
   int prec64 = 1;
+  int level = 0;                 // cascade level (grid of the coarse problem doubled `level` times)
   int thr[3] = {0, 0, 0}, ept[3] = {kE, kE, kE};
   size_t smem[3] = {0, 0, 0};
   std::vector<ProbDev> pd;       // each problem's descriptor in this precision
@@ -514,48 +535,75 @@ struct Group {
 // continues in FP64 from its iterate (written to its phi buffer and read
 // back as an FP64 initial point, the regularisation delta kept, the rest of
 // its step or Newton-step budget), and its counters add up over both runs.
-int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
-               gpe_result* results) {
-  if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
+// With nlevels > 1 the solve is Algorithm 3 over grids that double per
+// level: a problem that ends a coarse level (at level_tol) is prolonged and
+// starts the next level at the following host check while the others go on
+// with theirs; phi0s[i] holds the coarse initial data (phis[i] when
+// nlevels == 1), phis[i] receives the finest level's result.
+int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phi0s,
+               void* const* phis, gpe_result* results, int nlevels = 1, double level_tol = 0.0) {
+  if (!c || count < 1 || !probs || !phi0s || !phis || !results || nlevels < 1) return GPE_EINVAL;
   CHK(check_options(opts));
   const gpe_options o = *opts;
   const bool mixed = o.precision == GPE_PREC_MIXED;
-  const int ng = mixed ? 2 : 1;                  // group 0: the options' precision; group 1: FP64 continuation
+  // group index: level-major over precision slots (slot 0: the options'
+  // precision; slot 1: the FP64 continuation of a mixed solve)
+  const int np = mixed ? 2 : 1;
+  const int ng = np * nlevels;
+  const int last_lv = nlevels - 1;
+  auto gid = [&](int lv, int ps) { return lv * np + ps; };
+  // every level's problems: the coarse grid doubled per level
+  std::vector<gpe_problem> lp((size_t)nlevels * count);
+  for (int l = 0; l < nlevels; ++l)
+    for (int i = 0; i < count; ++i) {
+      gpe_problem q = probs[i];
+      for (int a = 0; a < 3; ++a) q.n[a] = a < q.dim ? q.n[a] << l : q.n[a];
+      lp[(size_t)l * count + i] = q;
+    }
   std::vector<Group> grp(ng);
-  grp[0].prec64 = mixed ? 0 : 1;
-  if (mixed) grp[1].prec64 = 1;
+  for (int l = 0; l < nlevels; ++l)
+    for (int ps = 0; ps < np; ++ps) {
+      grp[gid(l, ps)].level = l;
+      grp[gid(l, ps)].prec64 = (mixed && ps == 0) ? 0 : 1;
+    }
   int plan_step = o.step_at;
   for (int gi = 0; gi < ng; ++gi) {
     int sa;
-    pick_plan(c, count, probs, grp[gi].prec64 ? GPE_PREC_FP64 : GPE_PREC_MIXED, o, grp[gi].thr, grp[gi].ept, &sa);
-    if (gi == 0) plan_step = sa;
+    pick_plan(c, count, &lp[(size_t)grp[gi].level * count], grp[gi].prec64 ? GPE_PREC_FP64 : GPE_PREC_MIXED, o,
+              grp[gi].thr, grp[gi].ept, &sa);
+    if (gi == gid(last_lv, 0)) plan_step = sa;   // the finest level's plan places the step
   }
-  std::vector<ProbDev> pd0(count);
-  std::vector<double> vaxis((size_t)count * 3 * kMaxN);
+  std::vector<std::vector<ProbDev>> pdl(nlevels, std::vector<ProbDev>(count));
+  std::vector<double> vaxis((size_t)nlevels * count * 3 * kMaxN);
   const int dim = probs[0].dim;
-  for (int i = 0; i < count; ++i) {
-    if (!phis[i]) return GPE_EINVAL;
-    CHK(build_prob(&probs[i], &pd0[i], &vaxis[(size_t)i * 3 * kMaxN]));
-    if (pd0[i].dim != dim) return GPE_EINVAL;
-  }
+  for (int i = 0; i < count; ++i)
+    if (!phis[i] || !phi0s[i]) return GPE_EINVAL;
+  for (int l = 0; l < nlevels; ++l)
+    for (int i = 0; i < count; ++i) {
+      CHK(build_prob(&lp[(size_t)l * count + i], &pdl[l][i], &vaxis[((size_t)l * count + i) * 3 * kMaxN]));
+      if (pdl[l][i].dim != dim) return GPE_EINVAL;
+    }
+  const std::vector<ProbDev>& pd0 = pdl[0];
+  const std::vector<ProbDev>& pdf = pdl[last_lv];
   // geometry of each pass for each problem and group: points per thread
   // (8, or 4 for latency-bound problems by default) and workgroup size
   for (Group& g : grp) {
-    g.pd = pd0;
+    const std::vector<ProbDev>& pdg = pdl[g.level];
+    g.pd = pdg;
     for (int ax = 0; ax < 3; ++ax) {
-      if (g.ept[ax] == 0) g.ept[ax] = default_elems(pd0);
+      if (g.ept[ax] == 0) g.ept[ax] = default_elems(pdg);
       const int th = g.thr[ax];
       if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
       for (int i = 0; i < count && ax < dim; ++i) {
-        const int tl = pd0[i].nl[ax] / g.ept[ax];
+        const int tl = pdg[i].nl[ax] / g.ept[ax];
         if (tl > 256 || (th != 0 && th % tl != 0)) return GPE_EINVAL;
       }
     }
     for (int ax = 0; ax < dim; ++ax) {
       int thr_ax = 0;
       for (int i = 0; i < count; ++i) {
-        const int th = g.thr[ax] ? g.thr[ax] : default_threads(pd0, dim);
-        Geom ge = pass_geom(pd0[i], ax, ax > 0, th, 16, g.ept[ax]);
+        const int th = g.thr[ax] ? g.thr[ax] : default_threads(pdg, dim);
+        Geom ge = pass_geom(pdg[i], ax, ax > 0, th, 16, g.ept[ax]);
         g.pd[i].tiles[ax] = ge.tiles;
         g.pd[i].lanes[ax] = ge.lanes;
         g.smem[ax] = std::max(g.smem[ax], ge.smem);
@@ -572,7 +620,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   int step_at = plan_step;
   if (step_at < 0) {
     int maxt = 0;
-    for (int i = 0; i < count; ++i) maxt = std::max(maxt, grp[0].pd[i].tiles[dim - 1]);
+    for (int i = 0; i < count; ++i) maxt = std::max(maxt, grp[gid(last_lv, 0)].pd[i].tiles[dim - 1]);
     step_at = (dim == 1 || maxt <= 128) ? STEP_LAST_GROUP : STEP_KERNEL;
   }
   // a 1D problem is one pass of one workgroup: its step ends that pass
@@ -583,6 +631,18 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       g.pd[i].step_at = step_at;
       g.pd[i].prec64 = g.prec64;
     }
+  // cascade: each problem's prolonged initial data of its next level (the
+  // finest grid's size), and room for the prolongation's intermediate axes
+  void* lvbuf = nullptr;
+  size_t lv_stride = 0;
+  if (nlevels > 1) {
+    for (int i = 0; i < count; ++i) lv_stride = std::max<size_t>(lv_stride, (size_t)pdf[i].m * 16);
+    void *t0, *t1;
+    CHK(ws_get(c, WS_PROLONG0, lv_stride, &t0));
+    CHK(ws_get(c, WS_PROLONG1, lv_stride, &t1));
+    CHK(ws_get(c, WS_LEVEL0, lv_stride * count, &lvbuf));
+  }
+  auto level_buf = [&](int i) { return (void*)((char*)lvbuf + (size_t)i * lv_stride); };
   // STEP_FUSED alternates two state arrays and two first-pass partials
   // buffers by evaluation parity; an even chunk leaves the latest state in
   // the first array at every host check
@@ -625,14 +685,14 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     std::vector<int> nb(count);
     size_t tot = 0;
     for (int i = 0; i < count; ++i) {
-      nb[i] = (int)std::min<int64_t>((pd0[i].m + 255) / 256, 256);
+      nb[i] = (int)std::min<int64_t>((pd0[i].m + 255) / 256, 256);   // level-0 data
       tot += nb[i];
     }
     void *part, *hp;
     CHK(ws_get(c, WS_IMAG, tot * sizeof(double), &part));
     size_t at = 0;
     for (int i = 0; i < count; ++i) {
-      launch_max_imag(c->s, nb[i], phis[i], pd0[i].m, (double*)part + at);
+      launch_max_imag(c->s, nb[i], phi0s[i], pd0[i].m, (double*)part + at);
       at += nb[i];
     }
     HIPCHK(hipGetLastError());
@@ -667,10 +727,16 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       d.part1x = (double*)(A + L.off_p1x);
       d.partF = (double*)(A + L.off_pf);
       d.ticket = (int32_t*)(A + L.off_ticket);
-      d.v_axis = (const double*)dvax + (size_t)i * 3 * kMaxN;
+      d.v_axis = (const double*)dvax + ((size_t)grp[gi].level * count + i) * 3 * kMaxN;
     }
-  // every problem starts in group 0; the device descriptor array holds each
-  // problem's current one
+  // every problem starts in group 0 (level 0, the options' precision); the
+  // device descriptor array holds each problem's current one
+  auto level_opts = [&](int lv) {
+    gpe_options ol = o;
+    if (lv < last_lv) ol.tol = level_tol;
+    return ol;
+  };
+  std::vector<int> lev(count, 0);
   std::vector<int> gof(count, 0);
   std::vector<ProbDev> cur(count);
   for (int i = 0; i < count; ++i) cur[i] = grp[0].pd[i];
@@ -686,14 +752,24 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       }
   };
   build_maps();
-  for (int gi = 0; gi < ng; ++gi)
-    for (int ax = 0; ax < dim; ++ax) {
-      size_t cap = 0;   // room for every problem of the batch
-      for (int i = 0; i < count; ++i) cap += (size_t)grp[gi].pd[i].tiles[ax];
-      CHK(ws_get(c, WS_BMAP0 + 3 * gi + ax, cap * sizeof(int2), &grp[gi].dbm[ax]));
-    }
+  {
+    // one buffer, a region per group and pass with room for every problem
+    std::vector<size_t> at((size_t)ng * 3, 0);
+    size_t tot = 0;
+    for (int gi = 0; gi < ng; ++gi)
+      for (int ax = 0; ax < dim; ++ax) {
+        size_t cap = 0;
+        for (int i = 0; i < count; ++i) cap += (size_t)grp[gi].pd[i].tiles[ax];
+        at[(size_t)gi * 3 + ax] = tot;
+        tot += (cap * sizeof(int2) + 255) / 256 * 256;
+      }
+    void* bmb;
+    CHK(ws_get(c, WS_BMAP, tot, &bmb));
+    for (int gi = 0; gi < ng; ++gi)
+      for (int ax = 0; ax < dim; ++ax) grp[gi].dbm[ax] = (char*)bmb + at[(size_t)gi * 3 + ax];
+  }
   std::vector<SolverState> st(count);
-  for (int i = 0; i < count; ++i) init_state(st[i], o);
+  for (int i = 0; i < count; ++i) init_state(st[i], level_opts(0));
   // uploads (staging offsets keep the pieces apart)
   size_t so = 0;
   CHK(upload(c, dvax, vaxis.data(), vaxis.size() * sizeof(double), so));
@@ -711,7 +787,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
   const ProbDev* P = (const ProbDev*)dprob;
   SolverState* S = (SolverState*)dstate;
-  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd0[i].m, phis[i], grp[0].prec64);
+  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd0[i].m, phi0s[i], grp[0].prec64);
   HIPCHK(hipGetLastError());
 
   // profile: an event pair around the last-axis pass of every k-th
@@ -833,9 +909,20 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     if (o.use_graph) CHK(capture());
     return GPE_OK;
   };
-  // counters of each problem's finished FP32 run (mixed precision)
-  std::vector<SolverState> first(count);
-  std::vector<char> handed(count, 0);
+  // counters of each problem's finished runs (an FP32 run that handed over,
+  // earlier cascade levels), added to its last run's at the end
+  struct Bank {
+    int32_t outer = 0, inner = 0, nfe = 0, nfe64 = 0, bt = 0, rej = 0, nf = 0, nw = 0, no = 0, sw = 0;
+    int32_t mx[3] = {0, 0, 0};
+    bool capped = false;   // a cascade level stopped at its cap
+  };
+  std::vector<Bank> bank(count);
+  auto deposit = [&](int i, const SolverState& s, bool fp32) {
+    Bank& b = bank[i];
+    b.outer += s.outer; b.inner += s.inner_total; b.nfe += s.nfe; b.nfe64 += s.nfe64;
+    b.bt += s.backtracks; b.rej += s.rejections; b.nf += s.nfe_f; b.nw += s.nfe_w; b.no += s.nfe_o;
+    if (fp32) { b.mx[0] += s.nfe_f; b.mx[1] += s.nfe_w; b.mx[2] += s.nfe_o; }
+  };
   double pass_ms = 0.0;
   int64_t pass_n = 0;
   void* pin;
@@ -862,14 +949,18 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       rc = GPE_EDEVICE;
       break;
     }
-    const SolverState* hs = (const SolverState*)pin;
+    // a copy: the uploads below may move the staging buffer
+    const std::vector<SolverState> hs((const SolverState*)pin, (const SolverState*)pin + count);
     bool all = true;
     int64_t maxnfe = 0;
-    std::vector<int> hand;
+    std::vector<int> hand, adv;
     for (int i = 0; i < count; ++i) {
       maxnfe = std::max<int64_t>(maxnfe, hs[i].nfe);
-      if (hs[i].done && hs[i].status == kStatusStalled && gof[i] == 0 && mixed) hand.push_back(i);
-      else if (hs[i].done) done_host[i] = 1;
+      if (!done_host[i] && hs[i].done) {
+        if (hs[i].status == kStatusStalled && mixed && gof[i] % np == 0) hand.push_back(i);
+        else if (lev[i] < last_lv && (hs[i].status == GPE_OK || hs[i].status == GPE_NOT_CONVERGED)) adv.push_back(i);
+        else done_host[i] = 1;
+      }
       all = all && done_host[i];
     }
     if (o.profile) {
@@ -896,37 +987,52 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
     if (all) break;
     if (evals > cap) { rc = GPE_NOT_CONVERGED; break; }
-    // hand-overs: the FP32 iterate goes to the problem's phi buffer, comes
-    // back as the initial point of an FP64 run with the delta it reached and
-    // the rest of its budget
     size_t so2 = (sizeof(SolverState) * count + 255) / 256 * 256;   // staging past the state read-back
-    std::vector<SolverState> nst;
+    // a problem's new run: its descriptor in group `to`, a fresh state on
+    // both state arrays, and its initial data `phi0` (complex128)
+    auto restart = [&](int i, int to, const SolverState& s2, const void* phi0) -> int {
+      gof[i] = to;
+      cur[i] = grp[to].pd[i];
+      CHK(upload(c, (ProbDev*)dprob + i, &cur[i], sizeof(ProbDev), so2));
+      so2 += (sizeof(ProbDev) + 255) / 256 * 256;
+      CHK(upload(c, S + i, &s2, sizeof(SolverState), so2));
+      CHK(upload(c, S + count + i, &s2, sizeof(SolverState), so2));
+      so2 += (sizeof(SolverState) + 255) / 256 * 256;
+      launch_init(c->s, P, i, grp[to].pd[i].m, phi0, grp[to].prec64);
+      return GPE_OK;
+    };
+    // hand-overs: the FP32 iterate goes to the problem's phi buffer, comes
+    // back as the initial point of an FP64 run of the same level with the
+    // delta it reached and the rest of its budget
     for (int i : hand) {
-      first[i] = hs[i];
-      handed[i] = 1;
-      launch_write_phi(c->s, P, S, i, pd0[i].m, phis[i], 0);
-      gpe_options o2 = o;
+      deposit(i, hs[i], true);
+      bank[i].sw += std::max(1, hs[i].inner_total);
+      launch_write_phi(c->s, P, S, i, pdl[lev[i]][i].m, phis[i], 0);
+      const gpe_options ol = level_opts(lev[i]);
+      gpe_options o2 = ol;
       o2.precision = GPE_PREC_FP64;
-      if (o.algorithm == GPE_ALG1) o2.max_iter = std::max(0, o.max_iter - hs[i].inner_total);
-      else o2.max_outer = std::max(0, o.max_outer - hs[i].outer);
+      if (o.algorithm == GPE_ALG1) o2.max_iter = std::max(0, ol.max_iter - hs[i].inner_total);
+      else o2.max_outer = std::max(0, ol.max_outer - hs[i].outer);
       SolverState s2;
       init_state(s2, o2);
       if (o.algorithm != GPE_ALG1) s2.delta = std::min(std::max(hs[i].delta, o.delta_min), o.delta_max);
-      nst.push_back(s2);
+      CHK(restart(i, gid(lev[i], 1), s2, phis[i]));
     }
-    for (size_t k = 0; k < hand.size(); ++k) {
-      const int i = hand[k];
-      gof[i] = 1;
-      cur[i] = grp[1].pd[i];
-      CHK(upload(c, (ProbDev*)dprob + i, &cur[i], sizeof(ProbDev), so2));
-      so2 += (sizeof(ProbDev) + 255) / 256 * 256;
-      CHK(upload(c, S + i, &nst[k], sizeof(SolverState), so2));
-      CHK(upload(c, S + count + i, &nst[k], sizeof(SolverState), so2));
-      so2 += (sizeof(SolverState) + 255) / 256 * 256;
-      launch_init(c->s, P, i, pd0[i].m, phis[i], 1);
+    // cascade (Algorithm 3): a finished coarse level's iterate goes to the
+    // phi buffer, is prolonged to the next grid and starts that level's
+    // solve in the options' precision with a fresh state
+    for (int i : adv) {
+      deposit(i, hs[i], grp[gof[i]].prec64 == 0);
+      if (hs[i].status == GPE_NOT_CONVERGED) bank[i].capped = true;
+      launch_write_phi(c->s, P, S, i, pdl[lev[i]][i].m, phis[i], grp[gof[i]].prec64);
+      CHK(enqueue_prolong(c, pdl[lev[i]][i], phis[i], level_buf(i)));
+      ++lev[i];
+      SolverState s2;
+      init_state(s2, level_opts(lev[i]));
+      CHK(restart(i, gid(lev[i], 0), s2, level_buf(i)));
     }
     HIPCHK(hipGetLastError());
-    bool rebuild = !hand.empty();
+    bool rebuild = !hand.empty() || !adv.empty();
     for (int gi = 0; gi < ng && !rebuild; ++gi) {
       size_t act = 0;
       for (int i = 0; i < count; ++i)
@@ -949,7 +1055,18 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   if (rc < 0) return rc;
   HIPCHK(hipEventRecord(c->t1, c->s));
   std::memcpy(st.data(), pin, sizeof(SolverState) * count);
-  for (int i = 0; i < count; ++i) launch_write_phi(c->s, P, S, i, pd0[i].m, phis[i], grp[gof[i]].prec64);
+  for (int i = 0; i < count; ++i) {
+    launch_write_phi(c->s, P, S, i, pdl[lev[i]][i].m, phis[i], grp[gof[i]].prec64);
+    // a problem stopped on a coarse level (the solve's evaluation cap, an
+    // error) still returns a finest-grid function: its iterate prolonged
+    const void* src = phis[i];
+    for (int l = lev[i]; l < last_lv; ++l) {
+      void* dst = (src == phis[i]) ? level_buf(i) : phis[i];
+      CHK(enqueue_prolong(c, pdl[l][i], src, dst));
+      src = dst;
+    }
+    if (src != phis[i]) HIPCHK(hipMemcpyAsync(phis[i], src, (size_t)pdf[i].m * 16, hipMemcpyDeviceToDevice, c->s));
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->s));
   float ms = 0.0f;
@@ -959,53 +1076,40 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     gpe_result& r = results[i];
     std::memset(&r, 0, sizeof(r));
     const SolverState& s = st[i];
+    const Bank& b = bank[i];
     r.status = s.done ? s.status : GPE_NOT_CONVERGED;
+    if (lev[i] < last_lv && r.status == GPE_OK) r.status = GPE_NOT_CONVERGED;   // the cascade did not finish
+    if (b.capped && r.status == GPE_OK) r.status = GPE_NOT_CONVERGED;
     // a run still in its FP32 phase at the cap, or stopped there, counts its
-    // evaluations as mixed; a handed-over problem adds its FP32 run's
-    const bool in32 = mixed && gof[i] == 0;
-    r.outer_iters = s.outer;
-    r.inner_iters = s.inner_total;
-    r.nfe = s.nfe;
-    r.nfe_fp64 = s.nfe64;
-    r.backtracks = s.backtracks;
-    r.rejections = s.rejections;
+    // evaluations as mixed; earlier runs (FP32 before a hand-over, coarse
+    // levels) add theirs
+    const bool in32 = mixed && gof[i] % np == 0;
+    r.outer_iters = s.outer + b.outer;
+    r.inner_iters = s.inner_total + b.inner;
+    r.nfe = s.nfe + b.nfe;
+    r.nfe_fp64 = s.nfe64 + b.nfe64;
+    r.backtracks = s.backtracks + b.bt;
+    r.rejections = s.rejections + b.rej;
     r.delta = s.delta;
     r.time_ms = ms;
-    r.nfe_f = s.nfe_f;
-    r.nfe_w = s.nfe_w;
-    r.nfe_outer = s.nfe_o;
+    r.nfe_f = s.nfe_f + b.nf;
+    r.nfe_w = s.nfe_w + b.nw;
+    r.nfe_outer = s.nfe_o + b.no;
     r.pass_launches = (int32_t)pass_n;
     r.pass_ms = pass_ms;
-    if (in32) {
-      r.nfe_mixed[0] = s.nfe_f;
-      r.nfe_mixed[1] = s.nfe_w;
-      r.nfe_mixed[2] = s.nfe_o;
-    }
-    if (handed[i]) {
-      const SolverState& a = first[i];
-      r.switch_iter = std::max(1, a.inner_total);
-      r.outer_iters += a.outer;
-      r.inner_iters += a.inner_total;
-      r.nfe += a.nfe;
-      r.nfe_fp64 += a.nfe64;
-      r.backtracks += a.backtracks;
-      r.rejections += a.rejections;
-      r.nfe_f += a.nfe_f;
-      r.nfe_w += a.nfe_w;
-      r.nfe_outer += a.nfe_o;
-      r.nfe_mixed[0] = a.nfe_f;
-      r.nfe_mixed[1] = a.nfe_w;
-      r.nfe_mixed[2] = a.nfe_o;
-    }
+    r.switch_iter = b.sw;
+    r.nfe_mixed[0] = b.mx[0] + (in32 ? s.nfe_f : 0);
+    r.nfe_mixed[1] = b.mx[1] + (in32 ? s.nfe_w : 0);
+    r.nfe_mixed[2] = b.mx[2] + (in32 ? s.nfe_o : 0);
     if (r.status == kStatusStalled) r.status = GPE_NOT_CONVERGED;   // stopped before its continuation ran
     if (r.status >= 0) {
       // outputs recomputed in float64 from the returned phi
       double sc[10];
       ApplyArgs a{0, 0.0, phis[i], nullptr, nullptr};
       void* hout;
-      CHK(ws_get(c, WS_SCRATCH_OUT, (size_t)pd0[i].m * 16, &hout));
+      CHK(ws_get(c, WS_SCRATCH_OUT, (size_t)pdf[i].m * 16, &hout));
       a.out = hout;
-      CHK(run_apply(c, &probs[i], 1, a, sc));
+      CHK(run_apply(c, &lp[(size_t)last_lv * count + i], 1, a, sc));
       r.energy = sc[0];
       r.mu = sc[1];
       r.resid = sc[2];
@@ -1035,7 +1139,7 @@ int public_status(int st) {
 int solve_public(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_options* opts, void* const* phis,
                  gpe_result* results) {
   if (!c || count < 1 || !probs || !phis || !results) return GPE_EINVAL;
-  const int rc = solve_impl(c, count, probs, opts, phis, results);
+  const int rc = solve_impl(c, count, probs, opts, phis, phis, results);
   for (int i = 0; i < count; ++i) results[i].status = public_status(results[i].status);
   return public_status(rc);
 }
@@ -1317,7 +1421,7 @@ int gpe_autotune(gpe_ctx* c, const gpe_problem* prob, int32_t precision, int32_t
             CHK(end_call(c));
             gpe_result r;
             void* phis[1] = {buf};
-            CHK(solve_impl(c, 1, prob, &o, phis, &r));
+            CHK(solve_impl(c, 1, prob, &o, phis, phis, &r));
             if (r.nfe > 0) us = std::min(us, 1e3 * r.time_ms / r.nfe);
           }
           if (us < best) {
@@ -1352,21 +1456,7 @@ int gpe_prolong(gpe_ctx* c, const gpe_problem* coarse, const gpe_problem* fine, 
   for (int i = 0; i < dc.dim; ++i)
     if (df.n[i] != 2 * dc.n[i] || coarse->lo[i] != fine->lo[i] || coarse->hi[i] != fine->hi[i]) return GPE_EINVAL;
   CHK(begin_call(c));
-  int n[3] = {dc.n[0], dc.n[1], dc.n[2]};
-  const void* src = phi_c;
-  for (int ax = 0; ax < dc.dim; ++ax) {
-    void* dst;
-    if (ax == dc.dim - 1) dst = phi_f;
-    else {
-      int nn[3] = {n[0], n[1], n[2]};
-      nn[ax] *= 2;
-      CHK(ws_get(c, ax == 0 ? WS_PROLONG0 : WS_PROLONG1, (size_t)nn[0] * nn[1] * nn[2] * 16, &dst));
-    }
-    launch_prolong_axis(c->s, src, dst, n[0], n[1], n[2], ax, c->twd);
-    HIPCHK(hipGetLastError());
-    n[ax] *= 2;
-    src = dst;
-  }
+  CHK(enqueue_prolong(c, dc, phi_c, phi_f));
   return end_call(c);
 }
 
@@ -1375,89 +1465,9 @@ int gpe_solve_cascadic(gpe_ctx* c, int32_t count, const gpe_problem* coarse, int
   if (!c || count < 1 || !coarse || nlevels < 1 || !opts || !phi0s || !phis || !results) return GPE_EINVAL;
   for (int i = 0; i < count; ++i)
     if (coarse[i].bc != GPE_BC_FOURIER) return GPE_EUNSUPPORTED;   // trigonometric prolongation
-  std::vector<gpe_problem> lev(coarse, coarse + count);
-  // per-level buffers: two ping-pong sets of `count` complex128 arrays
-  size_t maxm = 0;
-  for (int i = 0; i < count; ++i) {
-    size_t m = 1;
-    for (int a = 0; a < coarse[i].dim; ++a) m *= (size_t)coarse[i].n[a] << (nlevels - 1);
-    maxm = std::max(maxm, m);
-  }
-  void *b0, *b1;
-  CHK(ws_get(c, WS_LEVEL0, maxm * 16 * count, &b0));
-  CHK(ws_get(c, WS_LEVEL1, maxm * 16 * count, &b1));
-  std::vector<void*> cur(count), nxt(count);
-  CHK(begin_call(c));
-  for (int i = 0; i < count; ++i) {
-    cur[i] = (char*)b0 + (size_t)i * maxm * 16;
-    nxt[i] = (char*)b1 + (size_t)i * maxm * 16;
-    size_t m = 1;
-    for (int a = 0; a < coarse[i].dim; ++a) m *= coarse[i].n[a];
-    HIPCHK(hipMemcpyAsync(cur[i], phi0s[i], m * 16, hipMemcpyDeviceToDevice, c->s));
-  }
-  CHK(end_call(c));
-  std::vector<gpe_result> tmp(count), tot(count);
-  for (int i = 0; i < count; ++i) std::memset(&tot[i], 0, sizeof(gpe_result));
-  int rc = GPE_OK;
-  for (int l = 0; l < nlevels; ++l) {
-    gpe_options o = *opts;
-    if (l < nlevels - 1) o.tol = level_tol;
-    std::vector<void*> dst(count);
-    for (int i = 0; i < count; ++i) dst[i] = (l == nlevels - 1) ? phis[i] : cur[i];
-    if (l == nlevels - 1)
-      for (int i = 0; i < count; ++i) {
-        size_t m = 1;
-        for (int a = 0; a < lev[i].dim; ++a) m *= lev[i].n[a];
-        CHK(begin_call(c));
-        HIPCHK(hipMemcpyAsync(phis[i], cur[i], m * 16, hipMemcpyDeviceToDevice, c->s));
-        CHK(end_call(c));
-      }
-    const int rl = solve_public(c, count, lev.data(), &o, dst.data(), tmp.data());
-    if (rl < 0) return rl;
-    // every counter adds up over the levels; the status is the worst one
-    // met on any level (a coarse level that stops at its cap is reported)
-    for (int i = 0; i < count; ++i) {
-      gpe_result& a = tot[i];
-      const gpe_result& b = tmp[i];
-      a.outer_iters += b.outer_iters; a.inner_iters += b.inner_iters;
-      a.nfe += b.nfe; a.nfe_fp64 += b.nfe_fp64;
-      a.backtracks += b.backtracks; a.rejections += b.rejections;
-      a.switch_iter += b.switch_iter;
-      a.nfe_f += b.nfe_f; a.nfe_w += b.nfe_w; a.nfe_outer += b.nfe_outer;
-      a.pass_launches += b.pass_launches; a.pass_ms += b.pass_ms;
-      for (int k = 0; k < 3; ++k) a.nfe_mixed[k] += b.nfe_mixed[k];
-      if (b.status < 0 && a.status >= 0) a.status = b.status;
-      else if (b.status == GPE_NOT_CONVERGED && a.status == GPE_OK) a.status = GPE_NOT_CONVERGED;
-    }
-    if (rl == GPE_NOT_CONVERGED) rc = GPE_NOT_CONVERGED;
-    tot[0].time_ms += tmp[0].time_ms;
-    if (l < nlevels - 1) {
-      for (int i = 0; i < count; ++i) {
-        gpe_problem fine = lev[i];
-        for (int a = 0; a < fine.dim; ++a) fine.n[a] *= 2;
-        CHK(gpe_prolong(c, &lev[i], &fine, cur[i], nxt[i]));
-        lev[i] = fine;
-      }
-      std::swap(cur, nxt);
-    }
-  }
-  // outputs of the finest level, counters of all levels
-  for (int i = 0; i < count; ++i) {
-    gpe_result r = tmp[i];
-    const gpe_result& a = tot[i];
-    r.status = a.status;
-    r.outer_iters = a.outer_iters; r.inner_iters = a.inner_iters;
-    r.nfe = a.nfe; r.nfe_fp64 = a.nfe_fp64;
-    r.backtracks = a.backtracks; r.rejections = a.rejections;
-    r.switch_iter = a.switch_iter;
-    r.nfe_f = a.nfe_f; r.nfe_w = a.nfe_w; r.nfe_outer = a.nfe_outer;
-    r.pass_launches = a.pass_launches; r.pass_ms = a.pass_ms;
-    for (int k = 0; k < 3; ++k) r.nfe_mixed[k] = a.nfe_mixed[k];
-    r.time_ms = tot[0].time_ms;
-    results[i] = r;
-    if (r.status < 0 && rc >= 0) rc = r.status;
-  }
-  return rc;
+  const int rc = solve_impl(c, count, coarse, opts, phi0s, phis, results, nlevels, level_tol);
+  for (int i = 0; i < count; ++i) results[i].status = public_status(results[i].status);
+  return public_status(rc);
 }
 
 }  // extern "C"

@@ -42,6 +42,9 @@ void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* 
 int noalloc_init(int device);
 char* noalloc_scratch(int device);
 void launch_setup_desc(hipStream_t s, const ProbDev& d, const VAxisParams& vp, ProbDev* dst, double* vaxis);
-void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
-                         const void* twd);
+// trigonometric prolongation of a complex128 array of shape (n0, n1, n2)
+// along axis `ax` (that length doubled in `out`); -1 for a length outside
+// 16 .. 512
+int launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
+                        const void* twd);
 }  // namespace gpe

@@ -265,48 +265,69 @@ __global__ void __launch_bounds__(256) k_retract_apply(const cx<T>* __restrict__
   }
 }
 
-// ---- trigonometric prolongation along one axis (n -> 2n points) ----
-// One workgroup per line; direct sums with the exact twiddle table.
-__global__ void __launch_bounds__(256) k_prolong_axis(const cx<double>* __restrict__ in, cx<double>* __restrict__ out,
-                                                      int n0, int n1, int n2, int ax,
-                                                      const cx<double>* __restrict__ tw) {
-  __shared__ cx<double> line[kMaxN / 2];
-  __shared__ cx<double> spec[kMaxN / 2];
-  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
-  const int64_t lines = (int64_t)n0 * n1 * n2 / n;
-  const int64_t L = blockIdx.x;
-  if (L >= lines) return;
-  // input strides and the line's base in the input and output arrays
-  int64_t bi, bo, si, so;
-  if (ax == 0) { bi = L * n0; bo = L * 2 * n0; si = 1; so = 1; }
+// ---- trigonometric prolongation along one axis (NC -> NF = 2 NC points) ----
+// Algorithm 3's interpolation of a coarse line: forward transform (NC
+// points, 4 per thread), the spectrum placed on the fine grid with the
+// coarse Nyquist mode split evenly between +NC/2 and -NC/2 and zeros above,
+// inverse transform (NF points, 8 per thread) scaled by 1/NC.  The two line
+// lengths use the same threads per line (NC/4 = NF/8).  A tile holds `lanes`
+// lines: consecutive rows along x (contiguous), else consecutive columns
+// (lane-interleaved, coalesced).  Input shape (a0, a1, a2); the output has
+// the axis doubled.  LDS: twiddles of NC and NF points, then the line data.
+template <int NC>
+__global__ void __launch_bounds__(256) k_prolong_fft(const cx<double>* __restrict__ in, cx<double>* __restrict__ out,
+                                                     int a0, int a1, int a2, int ax, int lanes,
+                                                     const cx<double>* __restrict__ tw) {
+  constexpr int NF = 2 * NC, TL = NC / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<double>* twc = reinterpret_cast<cx<double>*>(smem_raw);
+  cx<double>* twf = twc + NC;
+  cx<double>* data = twf + NF;
+  const bool strided = ax > 0;
+  LdsMap mp;
+  mp.lanes = lanes;
+  mp.strided = strided;
+  const int lane = strided ? threadIdx.x % lanes : threadIdx.x / TL;
+  const int t = strided ? threadIdx.x / lanes : threadIdx.x % TL;
+  const int64_t lines = (int64_t)a0 * a1 * a2 / NC;
+  const int64_t L0 = (int64_t)blockIdx.x * lanes + lane;
+  const bool act = L0 < lines;
+  const int64_t L = act ? L0 : 0;
+  int64_t bi, bo, st;
+  if (ax == 0) { bi = L * NC; bo = L * NF; st = 1; }
   else if (ax == 1) {
-    const int64_t x = L % n0, z = L / n0;
-    bi = z * (int64_t)n0 * n1 + x; bo = z * (int64_t)n0 * 2 * n1 + x; si = n0; so = n0;
-  } else { bi = L; bo = L; si = (int64_t)n0 * n1; so = (int64_t)n0 * n1; }
-  for (int j = threadIdx.x; j < n; j += blockDim.x) line[j] = in[bi + j * si];
+    const int64_t x = L % a0, z = L / a0;
+    bi = z * (int64_t)a0 * a1 + x; bo = z * (int64_t)a0 * 2 * a1 + x; st = a0;
+  } else { bi = L; bo = L; st = (int64_t)a0 * a1; }
+  TwiddleFetch<NC, double> fc;
+  TwiddleFetch<NF, double> ff;
+  fc.fetch(tw);
+  ff.fetch(tw);
+  cx<double> v[8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = in[bi + (int64_t)(t + e * TL) * st];
+  fc.store(twc);
+  ff.store(twf);
+  line_fft<NC, 4, false>(v, t, lane, mp, data, twc);   // starts with a barrier
+  __syncthreads();                                     // the last stage's LDS reads are done
+#pragma unroll
+  for (int e = 0; e < 4; ++e) data[mp.idx(lane, t + e * TL, NC)] = v[e];
   __syncthreads();
-  const int stp = kTwN / n;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {   // c_p = sum_j f_j exp(-2 pi i p j / n)
+  const double inv = 1.0 / NC;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int kf = t + e * TL;                 // fine frequency index, signed p
+    const int p = kf < NF / 2 ? kf : kf - NF;
+    const int ap = p < 0 ? -p : p;
     cx<double> c{0.0, 0.0};
-    for (int j = 0; j < n; ++j) c = c + cmul(line[j], tw[((int64_t)p * j * stp) & (kTwN - 1)]);
-    spec[p] = c;
+    if (ap < NC / 2) c = inv * data[mp.idx(lane, p < 0 ? p + NC : p, NC)];
+    else if (ap == NC / 2) c = (0.5 * inv) * data[mp.idx(lane, NC / 2, NC)];
+    v[e] = c;
   }
-  __syncthreads();
-  const int stf = kTwN / (2 * n);
-  const double inv = 1.0 / n;
-  for (int jf = threadIdx.x; jf < 2 * n; jf += blockDim.x) {
-    // (1/n) [ sum_{|p| < n/2} c_p e^{2 pi i p jf / 2n} + c_{n/2} cos(pi jf / 2) ]
-    cx<double> s{0.0, 0.0};
-    for (int p = -(n / 2) + 1; p < n / 2; ++p) {
-      const int pi = p < 0 ? p + n : p;
-      const int64_t k = ((int64_t)(p < 0 ? p + 2 * n : p) * jf * stf) & (kTwN - 1);
-      s = s + cmulc(spec[pi], tw[k]);   // spec * conj(exp(-...)) = spec * exp(+...)
-    }
-    const int jm = jf & 3;
-    const double cs = jm == 0 ? 1.0 : (jm == 2 ? -1.0 : 0.0);
-    s = s + cs * spec[n / 2];
-    out[bo + jf * so] = inv * s;
-  }
+  line_fft<NF, 8, true>(v, t, lane, mp, data, twf);    // starts with a barrier
+  if (act)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[bo + (int64_t)(t + e * TL) * st] = v[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -353,12 +374,30 @@ void launch_retract(hipStream_t s, int nblk, const void* x, const void* g, void*
 void launch_max_imag(hipStream_t s, int nblk, const void* x, int64_t m, double* part) {
   hipLaunchKernelGGL(k_max_imag, dim3(nblk), dim3(256), 0, s, (const cx<double>*)x, m, part);
 }
-void launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
-                         const void* twd) {
+int launch_prolong_axis(hipStream_t s, const void* in, void* out, int n0, int n1, int n2, int ax,
+                        const void* twd) {
   const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  const int tl = n / 4;
   const int64_t lines = (int64_t)n0 * n1 * n2 / n;
-  hipLaunchKernelGGL(k_prolong_axis, dim3((unsigned)lines), dim3(256), 0, s, (const cx<double>*)in, (cx<double>*)out,
-                     n0, n1, n2, ax, (const cx<double>*)twd);
+  int lanes = (int)std::min<int64_t>(std::max(1, 256 / tl), lines);
+  auto lds = [&](int ln) { return (size_t)(3 * n + lds_elems(2 * n, ln, ax > 0)) * sizeof(cx<double>); };
+  while (lanes > 1 && lds(lanes) > 65536) lanes /= 2;   // within 64 KB of LDS
+  const int64_t tiles = (lines + lanes - 1) / lanes;
+  const size_t smem = lds(lanes);
+  const dim3 g((unsigned)tiles), b((unsigned)(lanes * tl));
+  const cx<double>* a = (const cx<double>*)in;
+  cx<double>* o = (cx<double>*)out;
+  const cx<double>* w = (const cx<double>*)twd;
+  switch (n) {
+    case 16: hipLaunchKernelGGL(k_prolong_fft<16>, g, b, smem, s, a, o, n0, n1, n2, ax, lanes, w); break;
+    case 32: hipLaunchKernelGGL(k_prolong_fft<32>, g, b, smem, s, a, o, n0, n1, n2, ax, lanes, w); break;
+    case 64: hipLaunchKernelGGL(k_prolong_fft<64>, g, b, smem, s, a, o, n0, n1, n2, ax, lanes, w); break;
+    case 128: hipLaunchKernelGGL(k_prolong_fft<128>, g, b, smem, s, a, o, n0, n1, n2, ax, lanes, w); break;
+    case 256: hipLaunchKernelGGL(k_prolong_fft<256>, g, b, smem, s, a, o, n0, n1, n2, ax, lanes, w); break;
+    case 512: hipLaunchKernelGGL(k_prolong_fft<512>, g, b, smem, s, a, o, n0, n1, n2, ax, lanes, w); break;
+    default: return -1;
+  }
+  return 0;
 }
 
 }  // namespace gpe
