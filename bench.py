@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the last-axis pass per grid point, the canonical fused
 # pass set of the method's evaluation: the last pass reads the point and the
 # accumulated transforms of the other axes and writes the gradient, 3 b for
-# element size b (8 complex64, 16 complex128).
+# element size b (8 complex64, 16 complex128; half that for a real problem
+# whose arrays hold real values, result storage 2).
 CANON_LAST_PASS = 3
 
 # The solver's own model of the same pass, per mode (every array it reads or
@@ -259,11 +260,12 @@ def roofline(a, probs, results, cascade):
     ev32 = ev64 = 0
     for rs in results:
         for r, m in zip(rs, pts):
+            h = 0.5 if r["storage"] == 2 else 1.0     # real values, two points to an element
             for k, key in enumerate(("nfe_f", "nfe_w", "nfe_outer")):
                 mode = key[4]
                 n32 = r["nfe_mixed"][k]
-                byt += m * (n32 * mb[mode] + (r[key] - n32) * m64[mode])
-                canon += m * CANON_LAST_PASS * (8 * n32 + 16 * (r[key] - n32))
+                byt += h * m * (n32 * mb[mode] + (r[key] - n32) * m64[mode])
+                canon += h * m * CANON_LAST_PASS * (8 * n32 + 16 * (r[key] - n32))
                 ev32 += n32
                 ev64 += r[key] - n32
         nlaunch += max(r["nfe"] for r in rs)

@@ -126,12 +126,17 @@ typedef struct gpe_options {
                              HIP events: stamped by the kernel's own dispatch with plain launches
                              (use_graph 0), event record nodes around it inside a graph (these
                              add the event packets' time, a few microseconds); 0: off */
-    int32_t real_field;   /* -1 (default): real arithmetic when Omega = 0 for every problem and
-                             every phi0 has a zero imaginary part; 1: real arithmetic (Omega must
-                             be 0); 0: complex.  In real arithmetic the imaginary parts are
-                             dropped after every evaluation, so the iterates stay exactly real
-                             (the method on the unit sphere of R^M); otherwise rounding noise in
-                             them can grow and lead the iteration to a complex stationary state */
+    int32_t real_field;   /* -1 (default): real arithmetic for each problem with Omega = 0 whose
+                             phi0 has a zero imaginary part; 1: real arithmetic for every problem
+                             (Omega must be 0 for all); 0: complex.  In real arithmetic the
+                             iterates stay exactly real (the method on the unit sphere of R^M;
+                             otherwise rounding noise in their imaginary parts can grow and lead
+                             the iteration to a complex stationary state): a real problem on a
+                             Fourier grid in 2D or 3D keeps its arrays as real values, two grid
+                             points to a complex element, with half the bytes and transform work
+                             (two real lines per complex transform, the Omega = 0 multiplier
+                             being real and even); others drop the imaginary parts after every
+                             evaluation.  A problem's choice depends on its own phi0 only */
     int32_t threads[3];   /* workgroup size of the x, y, z passes (0 = built-in choice);
                              a multiple of 64 and of n/elems, at most 256 */
     int32_t step_at;      /* where the scalar step of the solver runs (GPE_STEP_*) */
@@ -189,7 +194,9 @@ typedef struct gpe_result {
     double pass_ms;       /* profile: summed event time of those launches */
     int32_t nfe_mixed[3]; /* of nfe_f, nfe_w, nfe_outer: the evaluations run by the mixed-precision
                              passes (the rest ran in an FP64 continuation or an FP64 solve) */
-    int32_t reserved2;
+    int32_t storage;      /* the solver's arrays: 0 complex; 1 real arithmetic in complex elements
+                             (imaginary parts dropped); 2 real values, two grid points to an
+                             element (see real_field) */
 } gpe_result;
 
 typedef struct gpe_ctx gpe_ctx;

@@ -70,7 +70,7 @@ class Result(C.Structure):
                 ("delta", C.c_double), ("time_ms", C.c_double),
                 ("nfe_f", C.c_int32), ("nfe_w", C.c_int32), ("nfe_outer", C.c_int32),
                 ("pass_launches", C.c_int32), ("pass_ms", C.c_double),
-                ("nfe_mixed", C.c_int32 * 3), ("reserved2", C.c_int32)]
+                ("nfe_mixed", C.c_int32 * 3), ("storage", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("rms", "nfe_mixed")}

@@ -224,7 +224,7 @@ Geom pass_geom(const ProbDev& d, int ax, bool strided, int threads, size_t elem,
   const int TL = N / ept;
   g.threads = threads < TL ? TL : threads;
   g.lanes = g.threads / TL;
-  const int64_t cols = d.m / d.n[ax];
+  const int64_t cols = (d.pair && ax == 0) ? d.m / d.nl[0] : d.m / d.n[ax];   // pair storage: x lines are row pairs
   g.tiles = (int)((cols + g.lanes - 1) / g.lanes);
   // twiddle table (N entries) + line data
   g.smem = ((size_t)N + (size_t)gpe::lds_elems_host(N, g.lanes, strided)) * elem;
@@ -523,6 +523,7 @@ int enqueue_prolong(gpe_ctx* c, const ProbDev& dc, const void* src, void* dst) {
 struct Group {
   int prec64 = 1;
   int level = 0;                 // cascade level (grid of the coarse problem doubled `level` times)
+  int pair = 0;                  // pair storage (real problems on Fourier grids, two or three dimensions)
   int thr[3] = {0, 0, 0}, ept[3] = {kE, kE, kE};
   size_t smem[3] = {0, 0, 0};
   std::vector<ProbDev> pd;       // each problem's descriptor in this precision
@@ -547,11 +548,12 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   const gpe_options o = *opts;
   const bool mixed = o.precision == GPE_PREC_MIXED;
   // group index: level-major over precision slots (slot 0: the options'
-  // precision; slot 1: the FP64 continuation of a mixed solve)
+  // precision; slot 1: the FP64 continuation of a mixed solve) over the
+  // storage (0: complex elements; 1: pair storage of a real problem)
   const int np = mixed ? 2 : 1;
-  const int ng = np * nlevels;
+  const int ng = np * nlevels * 2;
   const int last_lv = nlevels - 1;
-  auto gid = [&](int lv, int ps) { return lv * np + ps; };
+  auto gid = [&](int lv, int ps, int pr) { return (lv * np + ps) * 2 + pr; };
   // every level's problems: the coarse grid doubled per level
   std::vector<gpe_problem> lp((size_t)nlevels * count);
   for (int l = 0; l < nlevels; ++l)
@@ -562,16 +564,19 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
   std::vector<Group> grp(ng);
   for (int l = 0; l < nlevels; ++l)
-    for (int ps = 0; ps < np; ++ps) {
-      grp[gid(l, ps)].level = l;
-      grp[gid(l, ps)].prec64 = (mixed && ps == 0) ? 0 : 1;
-    }
+    for (int ps = 0; ps < np; ++ps)
+      for (int pr = 0; pr < 2; ++pr) {
+        Group& g = grp[gid(l, ps, pr)];
+        g.level = l;
+        g.prec64 = (mixed && ps == 0) ? 0 : 1;
+        g.pair = pr;
+      }
   int plan_step = o.step_at;
   for (int gi = 0; gi < ng; ++gi) {
     int sa;
     pick_plan(c, count, &lp[(size_t)grp[gi].level * count], grp[gi].prec64 ? GPE_PREC_FP64 : GPE_PREC_MIXED, o,
               grp[gi].thr, grp[gi].ept, &sa);
-    if (gi == gid(last_lv, 0)) plan_step = sa;   // the finest level's plan places the step
+    if (gi == gid(last_lv, 0, 0)) plan_step = sa;   // the finest level's plan places the step
   }
   std::vector<std::vector<ProbDev>> pdl(nlevels, std::vector<ProbDev>(count));
   std::vector<double> vaxis((size_t)nlevels * count * 3 * kMaxN);
@@ -585,29 +590,90 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
   const std::vector<ProbDev>& pd0 = pdl[0];
   const std::vector<ProbDev>& pdf = pdl[last_lv];
+  // real arithmetic forced: Omega = 0 required of every problem
+  bool no_rotation = true;
+  for (int i = 0; i < count; ++i) no_rotation = no_rotation && probs[i].omega == 0.0;
+  if (o.real_field == 1 && !no_rotation) return GPE_EINVAL;
+  CHK(begin_call(c));
+  // per problem: real arithmetic (forced, or automatic at Omega = 0 when its
+  // phi0 has a zero imaginary part), and pair storage for real problems on
+  // Fourier grids in two or three dimensions, which halves the arrays' bytes
+  // and the transform work; each problem's arithmetic depends on its own
+  // data only, so a batched problem keeps the bits it has alone
+  std::vector<int> realv(count, o.real_field == 1 ? 1 : 0), pairv(count, 0);
+  if (o.real_field < 0) {
+    std::vector<int> nb(count, 0);
+    size_t tot = 0;
+    for (int i = 0; i < count; ++i) {
+      if (probs[i].omega != 0.0) continue;
+      nb[i] = (int)std::min<int64_t>((pd0[i].m + 255) / 256, 256);   // level-0 data
+      tot += nb[i];
+    }
+    if (tot > 0) {
+      void *part, *hp;
+      CHK(ws_get(c, WS_IMAG, tot * sizeof(double), &part));
+      size_t at = 0;
+      for (int i = 0; i < count; ++i) {
+        if (nb[i] == 0) continue;
+        launch_max_imag(c->s, nb[i], phi0s[i], pd0[i].m, (double*)part + at);
+        at += nb[i];
+      }
+      HIPCHK(hipGetLastError());
+      CHK(pinned_get(c, tot * sizeof(double), &hp));
+      HIPCHK(hipMemcpyAsync(hp, part, tot * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+      at = 0;
+      for (int i = 0; i < count; ++i) {
+        if (nb[i] == 0) continue;
+        double mx = 0.0;
+        for (int k = 0; k < nb[i]; ++k) mx = std::max(mx, ((const double*)hp)[at + k]);
+        realv[i] = mx == 0.0 ? 1 : 0;
+        at += nb[i];
+      }
+    }
+  }
+  for (int i = 0; i < count; ++i) pairv[i] = realv[i] && dim >= 2 && probs[i].bc == GPE_BC_FOURIER ? 1 : 0;
+
   // geometry of each pass for each problem and group: points per thread
   // (8, or 4 for latency-bound problems by default) and workgroup size
+  // (a group's descriptors are those of its members: the problems whose
+  // storage matches it; the others' are left empty)
+  auto member = [&](const Group& g, int i) { return pairv[i] == g.pair; };
   for (Group& g : grp) {
-    const std::vector<ProbDev>& pdg = pdl[g.level];
-    g.pd = pdg;
+    g.pd = pdl[g.level];
+    std::vector<ProbDev> pdg;
+    for (int i = 0; i < count; ++i) {
+      ProbDev& d = g.pd[i];
+      if (!member(g, i)) continue;
+      if (g.pair) {   // the complex view of the pair storage
+        d.pair = 1;
+        d.n[0] /= 2;
+        d.stride[1] = d.n[0];
+        d.stride[2] = (int64_t)d.n[0] * d.n[1];
+        d.m /= 2;
+      }
+      pdg.push_back(d);
+    }
+    if (pdg.empty()) continue;
     for (int ax = 0; ax < 3; ++ax) {
       if (g.ept[ax] == 0) g.ept[ax] = default_elems(pdg);
       const int th = g.thr[ax];
       if (th != 0 && (th < 64 || th > 256 || th % 64 != 0)) return GPE_EINVAL;   // whole wavefronts
-      for (int i = 0; i < count && ax < dim; ++i) {
-        const int tl = pdg[i].nl[ax] / g.ept[ax];
+      for (size_t k = 0; k < pdg.size() && ax < dim; ++k) {
+        const int tl = pdg[k].nl[ax] / g.ept[ax];
         if (tl > 256 || (th != 0 && th % tl != 0)) return GPE_EINVAL;
       }
     }
     for (int ax = 0; ax < dim; ++ax) {
       int thr_ax = 0;
       for (int i = 0; i < count; ++i) {
+        if (!member(g, i)) continue;
         const int th = g.thr[ax] ? g.thr[ax] : default_threads(pdg, dim);
-        Geom ge = pass_geom(pdg[i], ax, ax > 0, th, 16, g.ept[ax]);
+        Geom ge = pass_geom(g.pd[i], ax, ax > 0, th, 16, g.ept[ax]);
         g.pd[i].tiles[ax] = ge.tiles;
         g.pd[i].lanes[ax] = ge.lanes;
         g.smem[ax] = std::max(g.smem[ax], ge.smem);
-        if (i == 0) thr_ax = ge.threads;
+        if (thr_ax == 0) thr_ax = ge.threads;
         else if (ge.threads != thr_ax) return GPE_EUNSUPPORTED;   // one workgroup size per pass
       }
       g.thr[ax] = thr_ax;
@@ -620,7 +686,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   int step_at = plan_step;
   if (step_at < 0) {
     int maxt = 0;
-    for (int i = 0; i < count; ++i) maxt = std::max(maxt, grp[gid(last_lv, 0)].pd[i].tiles[dim - 1]);
+    for (int i = 0; i < count; ++i) maxt = std::max(maxt, grp[gid(last_lv, 0, pairv[i])].pd[i].tiles[dim - 1]);
     step_at = (dim == 1 || maxt <= 128) ? STEP_LAST_GROUP : STEP_KERNEL;
   }
   // a 1D problem is one pass of one workgroup: its step ends that pass
@@ -657,6 +723,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   for (int gi = 0; gi < ng; ++gi)
     for (int i = 0; i < count; ++i) {
+      if (!member(grp[gi], i)) continue;
       const ProbDev& d = grp[gi].pd[i];
       const size_t m = (size_t)d.m, es = grp[gi].prec64 ? 16 : 8;   // element size of the F / W arrays
       ProbLayout& L = lay[(size_t)gi * count + i];
@@ -674,35 +741,6 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       L.off_pf = take((size_t)std::max(d.tiles[dim - 1], 1) * SF_COUNT * sizeof(double));
       L.off_ticket = take(64);
     }
-  // real arithmetic: forced (Omega = 0 required), or automatic when Omega = 0
-  // and every phi0 has a zero imaginary part (one max |Im| reduction each)
-  bool no_rotation = true;
-  for (int i = 0; i < count; ++i) no_rotation = no_rotation && probs[i].omega == 0.0;
-  if (o.real_field == 1 && !no_rotation) return GPE_EINVAL;
-  CHK(begin_call(c));
-  int real = o.real_field == 1 ? 1 : 0;
-  if (o.real_field < 0 && no_rotation) {
-    std::vector<int> nb(count);
-    size_t tot = 0;
-    for (int i = 0; i < count; ++i) {
-      nb[i] = (int)std::min<int64_t>((pd0[i].m + 255) / 256, 256);   // level-0 data
-      tot += nb[i];
-    }
-    void *part, *hp;
-    CHK(ws_get(c, WS_IMAG, tot * sizeof(double), &part));
-    size_t at = 0;
-    for (int i = 0; i < count; ++i) {
-      launch_max_imag(c->s, nb[i], phi0s[i], pd0[i].m, (double*)part + at);
-      at += nb[i];
-    }
-    HIPCHK(hipGetLastError());
-    CHK(pinned_get(c, tot * sizeof(double), &hp));
-    HIPCHK(hipMemcpyAsync(hp, part, tot * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    HIPCHK(hipStreamSynchronize(c->s));
-    double mx = 0.0;
-    for (size_t k = 0; k < tot; ++k) mx = std::max(mx, ((const double*)hp)[k]);
-    real = mx == 0.0 ? 1 : 0;
-  }
   void *arena, *dprob, *dstate, *dvax;
   CHK(ws_get(c, WS_ARENA, off, &arena));
   CHK(ws_get(c, WS_PROB, sizeof(ProbDev) * count, &dprob));
@@ -711,9 +749,10 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   char* A = (char*)arena;
   for (int gi = 0; gi < ng; ++gi)
     for (int i = 0; i < count; ++i) {
+      if (!member(grp[gi], i)) continue;
       const ProbLayout& L = lay[(size_t)gi * count + i];
       ProbDev& d = grp[gi].pd[i];
-      d.real = real;
+      d.real = grp[gi].pair ? 0 : realv[i];   // pair storage holds both points' values, no imaginary parts
       for (int k = 0; k < 2; ++k) {
         d.xf[k] = A + L.off_xf[k];
         d.gf[k] = A + L.off_gf[k];
@@ -739,7 +778,10 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   std::vector<int> lev(count, 0);
   std::vector<int> gof(count, 0);
   std::vector<ProbDev> cur(count);
-  for (int i = 0; i < count; ++i) cur[i] = grp[0].pd[i];
+  for (int i = 0; i < count; ++i) {
+    gof[i] = gid(0, 0, pairv[i]);
+    cur[i] = grp[gof[i]].pd[i];
+  }
   std::vector<char> done_host(count, 0);
   // block maps of every group: (problem, tile) of its unfinished problems
   auto build_maps = [&]() {
@@ -787,7 +829,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
   const ProbDev* P = (const ProbDev*)dprob;
   SolverState* S = (SolverState*)dstate;
-  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, pd0[i].m, phi0s[i], grp[0].prec64);
+  for (int i = 0; i < count; ++i) launch_init(c->s, P, i, cur[i].m, phi0s[i], grp[gof[i]].prec64);
   HIPCHK(hipGetLastError());
 
   // profile: an event pair around the last-axis pass of every k-th
@@ -839,12 +881,13 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       for (const Group& g : grp)
         if (!g.bm[0].empty())
           launch_solver_pass(c->s, R_FIRST, g.prec64, (int)g.bm[0].size(), g.thr[0], g.smem[0], P, s_in, s_new,
-                             bmap(g, 0), c->twd, c->twf, par, nullptr, nullptr, 0, fused ? 1 : 0, g.ept[0]);
+                             bmap(g, 0), c->twd, c->twf, par, nullptr, nullptr, 0, fused ? 1 : 0, g.ept[0],
+                             g.pair);
       if (dim == 3)
         for (const Group& g : grp)
           if (!g.bm[1].empty())
             launch_solver_pass(c->s, R_MID, g.prec64, (int)g.bm[1].size(), g.thr[1], g.smem[1], P, s_new, s_new,
-                               bmap(g, 1), c->twd, c->twf, par, nullptr, nullptr, 0, 0, g.ept[1]);
+                               bmap(g, 1), c->twd, c->twf, par, nullptr, nullptr, 0, 0, g.ept[1], g.pair);
     }
     if (nodes) record(pev[2 * k]);
     for (const Group& g : grp) {
@@ -856,7 +899,8 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       // 129 -> 146 us)
       const int reread = ((int64_t)g.bm[dim - 1].size() >= kRereadTiles && g.thr[dim - 1] >= 128) ? 1 : 0;
       launch_solver_pass(c->s, last, g.prec64, (int)g.bm[dim - 1].size(), g.thr[dim - 1], g.smem[dim - 1], P,
-                         s_new, s_new, bmap(g, dim - 1), c->twd, c->twf, par, e0, e1, reread, 0, g.ept[dim - 1]);
+                         s_new, s_new, bmap(g, dim - 1), c->twd, c->twf, par, e0, e1, reread, 0, g.ept[dim - 1],
+                         g.pair);
     }
     if (nodes) record(pev[2 * k + 1]);
     if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S);
@@ -957,7 +1001,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     for (int i = 0; i < count; ++i) {
       maxnfe = std::max<int64_t>(maxnfe, hs[i].nfe);
       if (!done_host[i] && hs[i].done) {
-        if (hs[i].status == kStatusStalled && mixed && gof[i] % np == 0) hand.push_back(i);
+        if (hs[i].status == kStatusStalled && mixed && grp[gof[i]].prec64 == 0) hand.push_back(i);
         else if (lev[i] < last_lv && (hs[i].status == GPE_OK || hs[i].status == GPE_NOT_CONVERGED)) adv.push_back(i);
         else done_host[i] = 1;
       }
@@ -1007,7 +1051,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     for (int i : hand) {
       deposit(i, hs[i], true);
       bank[i].sw += std::max(1, hs[i].inner_total);
-      launch_write_phi(c->s, P, S, i, pdl[lev[i]][i].m, phis[i], 0);
+      launch_write_phi(c->s, P, S, i, grp[gof[i]].pd[i].m, phis[i], 0);
       const gpe_options ol = level_opts(lev[i]);
       gpe_options o2 = ol;
       o2.precision = GPE_PREC_FP64;
@@ -1016,7 +1060,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       SolverState s2;
       init_state(s2, o2);
       if (o.algorithm != GPE_ALG1) s2.delta = std::min(std::max(hs[i].delta, o.delta_min), o.delta_max);
-      CHK(restart(i, gid(lev[i], 1), s2, phis[i]));
+      CHK(restart(i, gid(lev[i], 1, pairv[i]), s2, phis[i]));
     }
     // cascade (Algorithm 3): a finished coarse level's iterate goes to the
     // phi buffer, is prolonged to the next grid and starts that level's
@@ -1024,12 +1068,12 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     for (int i : adv) {
       deposit(i, hs[i], grp[gof[i]].prec64 == 0);
       if (hs[i].status == GPE_NOT_CONVERGED) bank[i].capped = true;
-      launch_write_phi(c->s, P, S, i, pdl[lev[i]][i].m, phis[i], grp[gof[i]].prec64);
+      launch_write_phi(c->s, P, S, i, grp[gof[i]].pd[i].m, phis[i], grp[gof[i]].prec64);
       CHK(enqueue_prolong(c, pdl[lev[i]][i], phis[i], level_buf(i)));
       ++lev[i];
       SolverState s2;
       init_state(s2, level_opts(lev[i]));
-      CHK(restart(i, gid(lev[i], 0), s2, level_buf(i)));
+      CHK(restart(i, gid(lev[i], 0, pairv[i]), s2, level_buf(i)));
     }
     HIPCHK(hipGetLastError());
     bool rebuild = !hand.empty() || !adv.empty();
@@ -1056,7 +1100,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   HIPCHK(hipEventRecord(c->t1, c->s));
   std::memcpy(st.data(), pin, sizeof(SolverState) * count);
   for (int i = 0; i < count; ++i) {
-    launch_write_phi(c->s, P, S, i, pdl[lev[i]][i].m, phis[i], grp[gof[i]].prec64);
+    launch_write_phi(c->s, P, S, i, grp[gof[i]].pd[i].m, phis[i], grp[gof[i]].prec64);
     // a problem stopped on a coarse level (the solve's evaluation cap, an
     // error) still returns a finest-grid function: its iterate prolonged
     const void* src = phis[i];
@@ -1083,7 +1127,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     // a run still in its FP32 phase at the cap, or stopped there, counts its
     // evaluations as mixed; earlier runs (FP32 before a hand-over, coarse
     // levels) add theirs
-    const bool in32 = mixed && gof[i] % np == 0;
+    const bool in32 = mixed && grp[gof[i]].prec64 == 0;
     r.outer_iters = s.outer + b.outer;
     r.inner_iters = s.inner_total + b.inner;
     r.nfe = s.nfe + b.nfe;
@@ -1098,6 +1142,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     r.pass_launches = (int32_t)pass_n;
     r.pass_ms = pass_ms;
     r.switch_iter = b.sw;
+    r.storage = pairv[i] ? 2 : (realv[i] ? 1 : 0);
     r.nfe_mixed[0] = b.mx[0] + (in32 ? s.nfe_f : 0);
     r.nfe_mixed[1] = b.mx[1] + (in32 ? s.nfe_w : 0);
     r.nfe_mixed[2] = b.mx[2] + (in32 ? s.nfe_o : 0);

@@ -12,11 +12,12 @@ namespace gpe {
 // by the dispatch itself at the kernel's start and end; reread (final and
 // solo roles): the epilogue re-reads the trial inputs; fused (first role):
 // the pass runs the previous evaluation's scalar step (STEP_FUSED); ept:
-// transform points per thread of the pass (8 or 4)
+// transform points per thread of the pass (8 or 4); pair: the problems store
+// real grid functions two points to an element (not the 1D pass)
 void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int threads, size_t smem,
                         const ProbDev* probs, SolverState* st_in, SolverState* st_out, const int2* bmap,
                         const void* twd, const void* twf, int par, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                        int reread = 0, int fused = 0, int ept = kE);
+                        int reread = 0, int fused = 0, int ept = kE, int pair = 0);
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
 // the scalar step of every problem (its precision from its descriptor)

@@ -81,6 +81,8 @@ struct ProbDev {
   int32_t step_at;       // StepAt: where the scalar step runs
   int32_t real;          // 1: drop the imaginary parts of every stored iterate and gradient
   int32_t prec64;        // 1: the problem's arrays and passes are float64 (else the mixed precision's)
+  int32_t pair;          // 1: a real grid function, two x-neighbours to a complex element (the solver's
+                         // arrays; n[0], strides and m describe that complex view, nl[0] the x lines)
   double lo[3], h[3], len[3];   // len: period of the transformed line (b-a, or 2(b-a) for sine)
   double x0[3];          // coordinate of array index 0 (lo, or lo + h for sine and finite differences)
   double ctr[3];         // centre of the box (lo + hi) / 2: Dirichlet grids take the coordinates of

@@ -31,11 +31,13 @@ __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict
 
 
 // ---- initial data: X_0 = sqrt(h_vol) phi_0 in the F-mode arrays, G = 0 ----
+// (pair storage: element g holds the real parts of points 2g and 2g + 1)
 template <typename TF>
 __global__ void k_init(const ProbDev* probs, int pi, const cx<double>* __restrict__ phi0) {
   const ProbDev& P = probs[pi];
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
-    stc<TF>(P.xf[0], g, realify(P, cvt<TF>(P.sqrt_hvol * phi0[g])));
+    const cx<double> u = P.pair ? cx<double>{phi0[2 * g].re, phi0[2 * g + 1].re} : phi0[g];
+    stc<TF>(P.xf[0], g, realify(P, cvt<TF>(P.sqrt_hvol * u)));
     stc<TF>(P.gf[0], g, cx<TF>{0, 0});
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *P.ticket = 0;
@@ -49,7 +51,12 @@ __global__ void k_write_phi(const ProbDev* probs, const SolverState* states, int
   const double sc = 1.0 / P.sqrt_hvol;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.m; g += (int64_t)gridDim.x * blockDim.x) {
     cx<double> x = (S.src == SRC_XF) ? cvt<double>(ld<TF>(P.xf[S.cur], g)) : reinterpret_cast<const cx<double>*>(P.xk)[g];
-    phi[g] = sc * x;
+    if (P.pair) {
+      phi[2 * g] = cx<double>{sc * x.re, 0.0};
+      phi[2 * g + 1] = cx<double>{sc * x.im, 0.0};
+    } else {
+      phi[g] = sc * x;
+    }
   }
 }
 

@@ -29,14 +29,26 @@ __device__ __forceinline__ int role_axis(int role, int dim) {
 // For finite differences position p reads array index p-1 and position 0
 // holds the boundary value 0; positions 1 .. N-1 are inner.
 // `P` is a local copy of the descriptor.
-template <int N, int EPT>
+// PAIR (real data, Fourier, Omega = 0, two or three dimensions): the arrays
+// hold the real grid function two points to a complex element, (x = 2c,
+// x = 2c + 1) at complex column c, and the descriptor describes that complex
+// view (n[0] = nx/2 columns, m = M/2 elements; nl[0] = nx is the x lines'
+// transform length).  The multipliers are real and even at Omega = 0, so a
+// transform of u + i w gives the results for u and w in its real and
+// imaginary parts: a strided pass transforms each complex column as the
+// pair of real columns 2c, 2c + 1; the x pass takes rows y and y + 1 of one
+// z slab as one complex line (tile lines are row pairs; the thread's first
+// E/2 elements come from row y, the others from row y + 1).
+template <int N, int EPT, bool PAIR = false>
 struct Tile {
   static constexpr int E = EPT, TL = N / E;
+  using VP = typename std::conditional<PAIR, cx<double>, double>::type;   // V at an element's point(s)
   int lanes, lane, t, ax;
   int c0, c1, c2;    // array coordinates of the line's first point (x, y, z)
   bool act, sine, fd;
-  int64_t base, st;
+  int64_t base, st, base2;   // base2: the second row of a PAIR x line
   double va[3];      // separable V tables at the line's fixed coordinates
+  double va0b;       // PAIR strided passes: V_x at the column pair's second point
   LdsMap mp;
   __device__ __forceinline__ Tile(const ProbDev& P, int ax_, bool strided, int tile) {
     ax = ax_;
@@ -46,18 +58,22 @@ struct Tile {
     if (strided) { lane = threadIdx.x % lanes; t = threadIdx.x / lanes; }
     else { lane = threadIdx.x / TL; t = threadIdx.x % TL; }
     const int col = tile * lanes + lane;
-    const int ncols = (int)(P.m / pick3(P.n, ax));
+    const int ncols = (PAIR && ax == 0) ? (int)(P.m / N) : (int)(P.m / pick3(P.n, ax));
     act = col < ncols;
     const int cc = act ? col : 0;
     const int n0 = P.n[0], n1 = P.n[1];
-    if (ax == 0) { c0 = 0; c1 = cc % n1; c2 = cc / n1; }
-    else if (ax == 1) { c0 = cc % n0; c1 = 0; c2 = cc / n0; }
+    if (ax == 0) {
+      if constexpr (PAIR) { c0 = 0; c1 = 2 * (cc % (n1 >> 1)); c2 = cc / (n1 >> 1); }
+      else { c0 = 0; c1 = cc % n1; c2 = cc / n1; }
+    } else if (ax == 1) { c0 = cc % n0; c1 = 0; c2 = cc / n0; }
     else { c0 = cc % n0; c1 = cc / n0; c2 = 0; }
     base = (int64_t)c0 + (int64_t)c1 * P.stride[1] + (int64_t)c2 * P.stride[2];
+    base2 = base + P.stride[1];
     st = pick3(P.stride, ax);
     // separable V: the tables at the line's fixed coordinates (unconditional
     // loads, in bounds of the [3][kMaxN] table; combined in pot_value)
-    va[0] = gld<double>(P.v_axis, c0);
+    va[0] = gld<double>(P.v_axis, PAIR ? 2 * c0 : c0);
+    va0b = PAIR ? gld<double>(P.v_axis, 2 * c0 + 1) : 0.0;
     va[1] = gld<double>(P.v_axis, kMaxN + c1);
     va[2] = gld<double>(P.v_axis, 2 * kMaxN + c2);
     mp.lanes = lanes;
@@ -85,27 +101,44 @@ struct Tile {
     const int p = pos(e);
     return act && (fd ? p > 0 : (!sine || (p > 0 && p < N / 2)));
   }
-  __device__ __forceinline__ int64_t g(int e) const { return base + (int64_t)idx(e) * st; }
+  __device__ __forceinline__ int64_t g(int e) const {
+    if constexpr (PAIR)
+      if (ax == 0) return (e < E / 2 ? base : base2) + (int64_t)(t + (e < E / 2 ? e : e - E / 2) * TL);
+    return base + (int64_t)idx(e) * st;
+  }
   // Potential at the thread's elements in two steps, so that the loads join
   // the tile's batch and the arithmetic waits until the values are used:
   // pot_load fetches the explicit V or this axis' table entries, pot_value
   // adds the other axes' entries.
-  __device__ __forceinline__ void pot_load(const ProbDev& P, double* vp) const {
-    if (P.has_v) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_arr, g(e));
+  // (PAIR: V at both points of the element; an explicit V array is read as
+  // its complex view too.  PAIR epilogues are strided passes, ax != 0.)
+  __device__ __forceinline__ VP pot_one(const ProbDev& P, int e) const {
+    if constexpr (PAIR) {
+      if (P.has_v) return gld<cx<double>>(P.v_arr, g(e));
+      const double v = gld<double>(P.v_axis, ax * kMaxN + idx(e));
+      return cx<double>{v, v};
     } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e) vp[e] = gld<double>(P.v_axis, ax * kMaxN + idx(e));
+      return P.has_v ? gld<double>(P.v_arr, g(e)) : gld<double>(P.v_axis, ax * kMaxN + idx(e));
     }
   }
-  __device__ __forceinline__ double pot_value(const ProbDev& P, double vpe) const {
+  __device__ __forceinline__ void pot_load(const ProbDev& P, VP* vp) const {
+#pragma unroll
+    for (int e = 0; e < E; ++e) vp[e] = pot_one(P, e);
+  }
+  __device__ __forceinline__ VP pot_value(const ProbDev& P, VP vpe) const {
     if (P.has_v) return vpe;
-    double vcol = 0.0;
-    if (ax != 0) vcol += va[0];
-    if (ax != 1 && P.dim > 1) vcol += va[1];
-    if (ax != 2 && P.dim > 2) vcol += va[2];
-    return vcol + vpe;
+    if constexpr (PAIR) {
+      double v0 = va[0], v1 = va0b;
+      if (ax != 1 && P.dim > 1) { v0 += va[1]; v1 += va[1]; }
+      if (ax != 2 && P.dim > 2) { v0 += va[2]; v1 += va[2]; }
+      return cx<double>{v0 + vpe.re, v1 + vpe.im};
+    } else {
+      double vcol = 0.0;
+      if (ax != 0) vcol += va[0];
+      if (ax != 1 && P.dim > 1) vcol += va[1];
+      if (ax != 2 && P.dim > 2) vcol += va[2];
+      return vcol + vpe;
+    }
   }
   // Omega * (coordinate entering this axis' first-derivative multiplier);
   // rotation is Fourier only
@@ -127,8 +160,8 @@ __device__ __forceinline__ CT axis_mult(int k, int n, CT two_pi_over_len, CT rc,
 // Finite differences (§2.1): -1/2 (u_{p+1} - 2 u_p + u_{p-1}) / h^2 along
 // the line through the LDS line buffer; u at position 0 is the boundary
 // value 0 (the caller's sign factor), the value past position N-1 the other.
-template <int N, int E, typename CT>
-__device__ __forceinline__ void fd_stencil(const ProbDev& P, int ax, const Tile<N, E>& T, cx<CT>* v,
+template <int N, int E, typename CT, bool PR>
+__device__ __forceinline__ void fd_stencil(const ProbDev& P, int ax, const Tile<N, E, PR>& T, cx<CT>* v,
                                            cx<CT>* lds) {
   cx<CT>* data = lds + N;
   __syncthreads();       // nobody still reads the LDS lines
@@ -165,8 +198,8 @@ __device__ __forceinline__ int* sine_flag_store() {
   __shared__ int f[64];   // lines per tile of a sine pass: at most 256 threads / 4
   return f;
 }
-template <int N, int E, typename CT>
-__device__ __forceinline__ void sine_parity_in(const Tile<N, E>& T, const cx<CT>* v, cx<CT>* data) {
+template <int N, int E, typename CT, bool PR>
+__device__ __forceinline__ void sine_parity_in(const Tile<N, E, PR>& T, const cx<CT>* v, cx<CT>* data) {
   constexpr int H = N / 2;
   int* flags = sine_flag_store();
   __syncthreads();       // nobody still reads the LDS lines
@@ -186,8 +219,8 @@ __device__ __forceinline__ void sine_parity_in(const Tile<N, E>& T, const cx<CT>
   }
   if (bad) atomicAnd(&flags[T.lane], ~bad);
 }
-template <int N, int E, typename CT>
-__device__ __forceinline__ void sine_parity_out(const Tile<N, E>& T, cx<CT>* v, cx<CT>* data) {
+template <int N, int E, typename CT, bool PR>
+__device__ __forceinline__ void sine_parity_out(const Tile<N, E, PR>& T, cx<CT>* v, cx<CT>* data) {
   constexpr int H = N / 2;
   const int* flags = sine_flag_store();
   __syncthreads();       // the last transform stage has read its LDS lines
@@ -211,8 +244,8 @@ __device__ __forceinline__ void sine_parity_out(const Tile<N, E>& T, cx<CT>* v, 
 // (spectral_inverse) of the tile's lines; spectral_apply is both.  `lds`
 // holds the twiddle table (N entries) followed by the line data.  Finite
 // differences apply their stencil in the forward half.
-template <int N, int E, typename CT>
-__device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const Tile<N, E>& T, cx<CT>* v,
+template <int N, int E, typename CT, bool PR>
+__device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const Tile<N, E, PR>& T, cx<CT>* v,
                                                  cx<CT>* lds) {
   if (T.fd) {
     fd_stencil<N, E, CT>(P, ax, T, v, lds);
@@ -229,16 +262,51 @@ __device__ __forceinline__ void spectral_forward(const ProbDev& P, int ax, const
     v[e] = mlt * v[e];
   }
 }
-template <int N, int E, typename CT>
-__device__ __forceinline__ void spectral_inverse(const Tile<N, E>& T, cx<CT>* v, cx<CT>* lds) {
+template <int N, int E, typename CT, bool PR>
+__device__ __forceinline__ void spectral_inverse(const Tile<N, E, PR>& T, cx<CT>* v, cx<CT>* lds) {
   if (!T.fd) line_fft<N, E, true>(v, T.t, T.lane, T.mp, lds + N, lds);
   if (T.sine) sine_parity_out<N, E, CT>(T, v, lds + N);
 }
-template <int N, int E, typename CT>
-__device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N, E>& T, cx<CT>* v,
+template <int N, int E, typename CT, bool PR>
+__device__ __forceinline__ void spectral_apply(const ProbDev& P, int ax, const Tile<N, E, PR>& T, cx<CT>* v,
                                                cx<CT>* lds) {
   spectral_forward<N, E, CT>(P, ax, T, v, lds);
   spectral_inverse<N, E, CT>(T, v, lds);
+}
+
+// PAIR x pass: the thread's storage elements (E/2 complex elements q = t +
+// j TL of row y, then of row y + 1, each the real points 2q, 2q + 1) to
+// transform order (position p: row y's point p as the real part, row y + 1's
+// as the imaginary part), through the LDS line area, and back.  Every thread
+// of the workgroup must call them (barriers).
+template <int N, int E, typename CT>
+__device__ __forceinline__ void pair_to_line(const Tile<N, E, true>& T, cx<CT>* v, cx<CT>* data) {
+  constexpr int H = E / 2, TL = N / E;
+  __syncthreads();       // nobody still reads the LDS lines
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const int q = T.t + j * TL;
+    data[T.mp.idx(T.lane, 2 * q, N)] = cx<CT>{v[j].re, v[j + H].re};
+    data[T.mp.idx(T.lane, 2 * q + 1, N)] = cx<CT>{v[j].im, v[j + H].im};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = data[T.mp.idx(T.lane, T.t + e * TL, N)];
+}
+template <int N, int E, typename CT>
+__device__ __forceinline__ void line_to_pair(const Tile<N, E, true>& T, cx<CT>* v, cx<CT>* data) {
+  constexpr int H = E / 2, TL = N / E;
+  __syncthreads();       // the last transform stage has read its LDS lines
+#pragma unroll
+  for (int e = 0; e < E; ++e) data[T.mp.idx(T.lane, T.t + e * TL, N)] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const int q = T.t + j * TL;
+    const cx<CT> w0 = data[T.mp.idx(T.lane, 2 * q, N)], w1 = data[T.mp.idx(T.lane, 2 * q + 1, N)];
+    v[j] = cx<CT>{w0.re, w1.re};
+    v[j + H] = cx<CT>{w0.im, w1.im};
+  }
 }
 
 // One slot of the fixed-order reduction (the same bits as that slot of the
@@ -322,9 +390,38 @@ template <typename T> __device__ __forceinline__ void stc(void* p, int64_t g, cx
 struct Acc1 { double ny = 0.0, np2 = 0.0, rmax = 0.0; };
 struct AccF { double s[SF_COUNT_SUM] = {}; double smax = 0.0; };
 
+// Point-wise arithmetic of the epilogues.  A complex element is one grid
+// point (Pw<false>: its density |v|^2 and products Re(conj(a) b) are
+// scalars), or under PAIR two real grid points (Pw<true>: densities and
+// products are pairs, one per point).  Sums over the grid (abs2, redot of
+// elements) are the same in both.
+template <bool PAIR> struct Pw {
+  using D = double;
+  static __device__ __forceinline__ D dens(cx<double> v) { return abs2(v); }
+  static __device__ __forceinline__ D pdot(cx<double> a, cx<double> b) { return redot(a, b); }
+  static __device__ __forceinline__ D prod(D a, D b) { return a * b; }
+  static __device__ __forceinline__ cx<double> mul(D s, cx<double> v) { return s * v; }
+  static __device__ __forceinline__ double sum(D s) { return s; }
+  static __device__ __forceinline__ double max2(cx<double> v) { return abs2(v); }   // largest |value|^2
+  // al * a * b summed over the element's points (in this order)
+  static __device__ __forceinline__ double asum(double al, D a, D b) { return al * a * b; }
+};
+template <> struct Pw<true> {
+  using D = cx<double>;
+  static __device__ __forceinline__ D dens(cx<double> v) { return {v.re * v.re, v.im * v.im}; }
+  static __device__ __forceinline__ D pdot(cx<double> a, cx<double> b) { return {a.re * b.re, a.im * b.im}; }
+  static __device__ __forceinline__ D prod(D a, D b) { return {a.re * b.re, a.im * b.im}; }
+  static __device__ __forceinline__ cx<double> mul(D s, cx<double> v) { return {s.re * v.re, s.im * v.im}; }
+  static __device__ __forceinline__ double sum(D s) { return s.re + s.im; }
+  static __device__ __forceinline__ double max2(cx<double> v) { return fmax(v.re * v.re, v.im * v.im); }
+  static __device__ __forceinline__ double asum(double al, D a, D b) { return al * a.re * b.re + al * a.im * b.im; }
+};
+
 // Algorithm 1 on F: Y = p X_b + q G_b.
-template <typename TF>
+template <typename TF, bool PAIR = false>
 struct FOps {
+  using W = Pw<PAIR>;
+  using D = typename W::D;
   struct In { cx<TF> x, g; };
   const ProbDev& P; const SolverState& S;
   const void *xb, *gb; void *xo, *go;
@@ -338,27 +435,27 @@ struct FOps {
   __device__ __forceinline__ void metrics1(const In& in, cx<double> y, Acc1& a) const {
     const cx<double> x = cvt<double>(in.x), gr = cvt<double>(in.g);
     a.np2 += abs2(S.n_b * gr - S.a_b * x);
-    a.rmax = fmax(a.rmax, abs2(gr - (S.a_b / S.n_b) * x));
+    a.rmax = fmax(a.rmax, W::max2(gr - (S.a_b / S.n_b) * x));
     a.ny += abs2(y);
   }
   // kin: kinetic(+rotation) part of H_lin applied to the unscaled trial
-  __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c,
+  __device__ __forceinline__ void final_(const In& in, int64_t g, D vg, cx<double> kin, double c,
                                          double n_hat, AccF& a) const {
     const cx<double> x = cvt<double>(in.x), gr = cvt<double>(in.g);
     const cx<TF> ys = realify(P, cvt<TF>(c * trial(in)));
     const cx<double> y = cvt<double>(ys);
-    const double q = abs2(y);
-    const cx<double> ay = 2.0 * (c * kin + vg * y);
-    const cx<TF> gs = realify(P, cvt<TF>(ay + (4.0 * P.alpha * q) * y));
+    const D q = W::dens(y);
+    const cx<double> ay = 2.0 * (c * kin + W::mul(vg, y));
+    const cx<TF> gs = realify(P, cvt<TF>(ay + W::mul(4.0 * P.alpha * q, y)));
     const cx<double> gy = cvt<double>(gs);
     stc<TF>(xo, g, ys);
     stc<TF>(go, g, gs);
-    a.s[SF_F] += 0.5 * redot(y, ay) + P.alpha * q * q;
+    a.s[SF_F] += 0.5 * redot(y, ay) + W::asum(P.alpha, q, q);
     const cx<double> s = y - x;
     const cx<double> w0 = n_hat * gy - S.n_b * gr - S.a_b * s;
     a.s[SF_A] += redot(y, gy);
     a.s[SF_NG] += abs2(gy);
-    a.s[SF_NY] += q;
+    a.s[SF_NY] += W::sum(q);
     a.s[SF_SS] += abs2(s);
     a.s[SF_SY] += redot(s, y);
     a.s[SF_SG] += redot(s, gy);
@@ -366,14 +463,16 @@ struct FOps {
     a.s[SF_W0W0] += abs2(w0);
     a.s[SF_W0G] += redot(w0, gy);
     a.s[SF_W0Y] += redot(w0, y);
-    a.smax = fmax(a.smax, abs2(s));
+    a.smax = fmax(a.smax, W::max2(s));
   }
 };
 
 // Newton subproblem, delta form: X = X_k + S, grad_W = G_k + D,
 // S_new = (p-1) X_k + p S_b + q (G_k + D_b).
-template <typename TW>
+template <typename TW, bool PAIR = false>
 struct WOps {
+  using W = Pw<PAIR>;
+  using D = typename W::D;
   struct In { cx<double> xk, gk; cx<TW> s, d; };
   const ProbDev& P; const SolverState& S;
   const void *xk, *gk, *sb, *db; void *so, *dout;
@@ -392,30 +491,31 @@ struct WOps {
     const cx<double> s = cvt<double>(in.s), d = cvt<double>(in.d);
     const cx<double> gb = in.gk + d, xb = in.xk + s;
     a.np2 += abs2((S.n_b * in.gk - S.a_b * in.xk) + (S.n_b * d - S.a_b * s));
-    a.rmax = fmax(a.rmax, abs2(gb - (S.a_b / S.n_b) * xb));
+    a.rmax = fmax(a.rmax, W::max2(gb - (S.a_b / S.n_b) * xb));
     a.ny += abs2(in.xk + sn);
   }
-  __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c,
+  __device__ __forceinline__ void final_(const In& in, int64_t g, D vg, cx<double> kin, double c,
                                          double n_hat, AccF& a) const {
     const cx<double> x0 = in.xk, g0 = in.gk;
     const cx<double> s = cvt<double>(in.s), d = cvt<double>(in.d);
     const cx<double> sn = trial(in);
-    const double qk = abs2(x0);
+    const D qk = W::dens(x0);
     const double al4 = 4.0 * P.alpha;
-    const cx<double> axk = g0 - (al4 * qk) * x0;                     // A X_k
+    const cx<double> axk = g0 - W::mul(al4 * qk, x0);                 // A X_k
     const cx<TW> ss = realify(P, cvt<TW>(c * sn + (c - 1.0) * x0));   // renormalised S
     const cx<double> sv = cvt<double>(ss);
-    const cx<double> as = c * (2.0 * (kin + vg * sn)) + (c - 1.0) * axk;  // A S
-    const cx<TW> ds = realify(P, cvt<TW>(as + al4 * (qk * sv + (2.0 * redot(x0, sv)) * x0) + S.delta * sv));
+    const cx<double> as = c * (2.0 * (kin + W::mul(vg, sn))) + (c - 1.0) * axk;  // A S
+    const cx<TW> ds = realify(P, cvt<TW>(as + al4 * (W::mul(qk, sv) + W::mul(2.0 * W::pdot(x0, sv), x0)) +
+                                         S.delta * sv));
     const cx<double> dv = cvt<double>(ds);
     stc<TW>(so, g, ss);
     stc<TW>(dout, g, ds);
     const cx<double> y = x0 + sv, gy = g0 + dv;
-    const double ny = abs2(y);
+    const D ny = W::dens(y);
     a.s[SF_F] += redot(sv, g0) + 0.5 * redot(sv, dv);
     a.s[SF_A] += redot(y, gy);
     a.s[SF_NG] += abs2(gy);
-    a.s[SF_NY] += ny;
+    a.s[SF_NY] += W::sum(ny);
     const cx<double> sb_ = sv - s;
     const cx<double> w0 = (n_hat - S.n_b) * g0 + n_hat * dv - S.n_b * d - S.a_b * sb_;
     a.s[SF_SS] += abs2(sb_);
@@ -426,14 +526,16 @@ struct WOps {
     a.s[SF_W0G] += redot(w0, gy);
     a.s[SF_W0Y] += redot(w0, y);
     a.s[SF_ARED] += redot(sv, axk) + 0.5 * redot(sv, as)
-                    + P.alpha * (2.0 * redot(x0, sv) + abs2(sv)) * (ny + qk);
-    a.smax = fmax(a.smax, abs2(sb_));
+                    + W::asum(P.alpha, 2.0 * W::pdot(x0, sv) + W::dens(sv), ny + qk);
+    a.smax = fmax(a.smax, W::max2(sb_));
   }
 };
 
 // Float64 evaluation at a new outer iterate; writes X_k, G_k and clears S/D.
-template <typename TF, typename TW>
+template <typename TF, typename TW, bool PAIR = false>
 struct OOps {
+  using W = Pw<PAIR>;
+  using D = typename W::D;
   struct In { cx<double> y, x0; };     // the point before renormalisation, and the old X_k
   const ProbDev& P; const SolverState& S;
   void *xk, *gk; const void *xf, *sc;
@@ -454,21 +556,21 @@ struct OOps {
   }
   __device__ __forceinline__ cx<double> trial(const In& in) const { return in.y; }
   __device__ __forceinline__ void metrics1(const In&, cx<double> y, Acc1& a) const { a.ny += abs2(y); }
-  __device__ __forceinline__ void final_(const In& in, int64_t g, double vg, cx<double> kin, double c, double,
+  __device__ __forceinline__ void final_(const In& in, int64_t g, D vg, cx<double> kin, double c, double,
                                          AccF& a) const {
     const cx<double> y = realify(P, c * in.y);
-    const double q = abs2(y);
-    const cx<double> ay = 2.0 * (c * kin + vg * y);
-    const cx<double> gy = realify(P, ay + (4.0 * P.alpha * q) * y);
+    const D q = W::dens(y);
+    const cx<double> ay = 2.0 * (c * kin + W::mul(vg, y));
+    const cx<double> gy = realify(P, ay + W::mul(4.0 * P.alpha * q, y));
     stc<double>(xk, g, y);
     stc<double>(gk, g, gy);
     stc<TW>(P.s[0], g, cx<TW>{0, 0});
     stc<TW>(P.d[0], g, cx<TW>{0, 0});
-    a.s[SF_F] += 0.5 * redot(y, ay) + P.alpha * q * q;
+    a.s[SF_F] += 0.5 * redot(y, ay) + W::asum(P.alpha, q, q);
     a.s[SF_A] += redot(y, gy);
     a.s[SF_NG] += abs2(gy);
-    a.s[SF_NY] += q;
-    a.smax = fmax(a.smax, abs2(y - in.x0));      // |X_{k+1} - X_k|^2 (Newton step lengths)
+    a.s[SF_NY] += W::sum(q);
+    a.smax = fmax(a.smax, W::max2(y - in.x0));   // |X_{k+1} - X_k|^2 (Newton step lengths)
   }
 };
 
@@ -485,18 +587,20 @@ struct OOps {
 // pass from one wavefront per SIMD to two, which pays where the launch has
 // enough tiles to be bandwidth bound and costs a little latency where not.
 // ---------------------------------------------------------------------------
-template <int N, int E, int ROLE, typename CT, class Ops, bool RR>
+// PAIR: see Tile (the x pass regroups its row pairs into transform lines
+// and back through LDS).
+template <int N, int E, int ROLE, typename CT, class Ops, bool RR, bool PAIR>
 __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState& S, int tile, const Ops& ops,
                                             cx<CT>* lds, const cx<CT>* tw1024, double* red) {
   constexpr bool HAS_T = (ROLE == R_MID || ROLE == R_FINAL);
   constexpr bool EPI = (ROLE == R_FINAL || ROLE == R_SOLO);
   const int ax = role_axis(ROLE, P.dim);
-  const Tile<N, E> T(P, ax, HAS_T, tile);
+  const Tile<N, E, PAIR> T(P, ax, HAS_T, tile);
   TwiddleFetch<N, CT> twf;
   twf.fetch(tw1024);
   typename Ops::In in[E];
   cx<CT> tv[E];
-  double vp[E];
+  typename Tile<N, E, PAIR>::VP vp[E];
   constexpr bool LATE = EPI && RR;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -535,7 +639,9 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
     c = renorm_c(S, bc);
     n_hat = c * c * bc;
   }
+  if constexpr (PAIR && ROLE == R_FIRST) pair_to_line<N, E, CT>(T, v, lds + N);
   spectral_apply<N, E, CT>(P, ax, T, v, lds);
+  if constexpr (PAIR && ROLE == R_FIRST) line_to_pair<N, E, CT>(T, v, lds + N);
   if constexpr (ROLE == R_FIRST) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -563,7 +669,7 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
         for (int e = hh * (E / G); e < (hh + 1) * (E / G); ++e) {
           in[e] = ops.load(T.g(e));
           if constexpr (HAS_T) tv[e] = ld<CT>(P.t, T.g(e));
-          vp[e] = P.has_v ? gld<double>(P.v_arr, T.g(e)) : gld<double>(P.v_axis, ax * kMaxN + T.idx(e));
+          vp[e] = T.pot_one(P, e);
         }
       }
 #pragma unroll
@@ -702,28 +808,31 @@ __device__ __forceinline__ void pin_desc_fields(ProbDev& P) {
 }
 
 // Dispatch on the problem's mode.  PREC64: every array float64.
-template <int N, int E, int ROLE, bool PREC64, bool RR>
+template <int N, int E, int ROLE, bool PREC64, bool RR, bool PAIR>
 __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverState& S, int tile, char* smem,
                                                 const cx<double>* twd, const cx<float>* twf, double* red) {
   using TS = typename std::conditional<PREC64, double, float>::type;   // F/W storage and transforms
   const cx<TS>* tws = PREC64 ? reinterpret_cast<const cx<TS>*>(twd) : reinterpret_cast<const cx<TS>*>(twf);
   if (S.mode == M_F) {
-    FOps<TS> ops(P, S);
-    solver_tile<N, E, ROLE, TS, FOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
+    using O = FOps<TS, PAIR>;
+    O ops(P, S);
+    solver_tile<N, E, ROLE, TS, O, RR, PAIR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_W) {
-    WOps<TS> ops(P, S);
-    solver_tile<N, E, ROLE, TS, WOps<TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
+    using O = WOps<TS, PAIR>;
+    O ops(P, S);
+    solver_tile<N, E, ROLE, TS, O, RR, PAIR>(P, S, tile, ops, reinterpret_cast<cx<TS>*>(smem), tws, red);
   } else if (S.mode == M_OUTER) {
-    OOps<TS, TS> ops(P, S);
-    solver_tile<N, E, ROLE, double, OOps<TS, TS>, RR>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd,
-                                                   red);
+    using O = OOps<TS, TS, PAIR>;
+    O ops(P, S);
+    solver_tile<N, E, ROLE, double, O, RR, PAIR>(P, S, tile, ops, reinterpret_cast<cx<double>*>(smem), twd, red);
   }
 }
 
 // `bmap` maps a workgroup to (problem, tile); null for a single problem
 // (workgroup b is tile b of problem 0).  EPT: transform points per thread
-// (8 or 4; the host launches the instance of its plan).  RR: see
-// solver_tile.  FUSED (first
+// (8 or 4; the host launches the instance of its plan).  PAIR: real grid
+// functions two points to an element (see Tile; every problem of the launch
+// is so stored).  RR: see solver_tile.  FUSED (first
 // pass only): the pass runs the previous evaluation's scalar step first
 // (STEP_FUSED; an instance of its own, so that the other instances carry
 // none of its code and registers).  The passes
@@ -731,7 +840,7 @@ __device__ __forceinline__ void solver_dispatch(const ProbDev& P, const SolverSt
 // after its step in st_out (the host alternates two state arrays and passes
 // the evaluation's parity `par`, which also selects the first-pass partials
 // buffer); otherwise st_out is st_in and par is 0.
-template <int ROLE, bool PREC64, bool RR, bool FUSED, int EPT>
+template <int ROLE, bool PREC64, bool RR, bool FUSED, int EPT, bool PAIR>
 __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__ probs,
                                                      SolverState* __restrict__ st_in,
                                                      SolverState* __restrict__ st_out,
@@ -759,7 +868,7 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
   const int n = pick3(P.nl, role_axis(ROLE, P.dim));
 #define GPE_SOLVER_CASE(NN)                                                   \
   case NN:                                                                    \
-    solver_dispatch<NN, EPT, ROLE, PREC64, RR>(P, S, bm.y, smem, twd, twf, red); \
+    solver_dispatch<NN, EPT, ROLE, PREC64, RR, PAIR>(P, S, bm.y, smem, twd, twf, red); \
     break;
   switch (n) {
     GPE_SOLVER_CASE(16) GPE_SOLVER_CASE(32) GPE_SOLVER_CASE(64) GPE_SOLVER_CASE(128)

@@ -66,7 +66,7 @@ def test_roofline_prices_the_canonical_last_pass():
     import workloads as W
     p, _ = W.rotating_2d()
     r = {"nfe": 1000, "nfe_f": 100, "nfe_w": 880, "nfe_outer": 20, "nfe_mixed": [100, 300, 0],
-         "pass_launches": 50, "pass_ms": 50 * 0.010}
+         "pass_launches": 50, "pass_ms": 50 * 0.010, "storage": 0}
     a = argparse.Namespace(workload="harm1d", profile_every=61)
     roof = bench.roofline(a, [p], [[r]], cascade=False)
     m = 256 * 256
@@ -77,3 +77,7 @@ def test_roofline_prices_the_canonical_last_pass():
     model = m * (100 * 40 + 300 * 72 + 580 * 112 + 20 * 112) / 1000
     assert roof["solver_model_bytes_per_launch"] == round(model)
     assert bench.roofline(a, [p], [[r]], cascade=True)["achieved"] is None
+    # real values two points to an element (storage 2): half the bytes of every array
+    half = bench.roofline(a, [p], [[dict(r, storage=2)]], cascade=False)
+    assert half["bytes_per_launch"] == round(canon / 2)
+    assert half["solver_model_bytes_per_launch"] == round(model / 2)

@@ -65,10 +65,11 @@ CASES = {"rot2d": W.rotating_2d, "lattice3d": W.lattice_3d}
 # (residual <= 1e-8 after the FP64 polish) but is another stationary state
 # than the oracle's, so (i) and (iii) do not apply.
 _LATTICE_MIXED = pytest.mark.xfail(
-    reason="3D lattice, mixed precision: the FP32 phase commits the iteration to another stationary state, "
-           "E = 52.0373910111 against the oracle's 52.0373904479 (1.08e-8 relative above it; the FP64 path "
-           "lands on the oracle's to 4e-14); the same state with the hand-over at 1e-2, 1e-3 or 1e-4 and "
-           "with Algorithm 1 alone, and the FP64 polish to 1e-8 leaves it there",
+    reason="3D lattice, mixed precision: the FP32 phase commits the iteration to another stationary state "
+           "of the weakly coupled lattice wells (complex storage: E = 52.0373910111, 1.08e-8 relative above "
+           "the oracle's 52.0373904479; real storage, two points to an element: E = 52.0373953398, 9.4e-8 "
+           "above); the FP64 path lands on the oracle's state to 4e-14, and the FP64 polish to 1e-8 leaves "
+           "the mixed path's state where it is",
     strict=False)
 # The isotropic rotating trap is invariant under rotations about the origin
 # (the spectral grid breaks this only at the level of its discretization

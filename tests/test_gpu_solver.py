@@ -347,6 +347,38 @@ def test_real_field_option(dev):
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["2d-explicit-v", "3d-lattice"])
+def test_real_pair_storage(dev, case, prec):
+    # real data on a Fourier grid at Omega = 0: the solver keeps real values,
+    # two grid points to a complex element (storage 2), and reaches the
+    # oracle's ground state as the complex storage (real_field = 0) does; the
+    # 2D case reads an explicit, x-asymmetric potential array in pair storage
+    if case == "2d-explicit-v":
+        q = W.Problem(dim=2, n=(64, 32), lo=(-8.0, -6.0), hi=(8.0, 6.0), beta=300.0)
+        x, y = disc.grid_coords(q)
+        v = 0.5 * (x * x + 2.0 * y * y) + 0.3 * x + 2.0 * np.sin(np.pi * x / 4) ** 2
+        p = W.Problem(dim=2, n=(64, 32), lo=(-8.0, -6.0), hi=(8.0, 6.0), beta=300.0, v=v)
+        phi0 = W.gaussian_times_noise(p, 0.02, 41)
+        vt = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+    else:
+        p = W.Problem(dim=3, n=(32, 32, 16), lo=(-8.0,) * 3, hi=(8.0,) * 3, beta=200.0, lattice_amp=10.0)
+        phi0, vt = W.gaussian_times_noise(p, 0.02, 42), None
+    up = UnifiedProblem(p)
+    ref = regularized_newton(up, up.to_x(phi0), Options(tol=1e-8))
+    assert ref.converged
+    for rf, storage in ((-1, 2), (0, 0)):
+        out, res = dev.solve(p, torch.from_numpy(np.asarray(phi0 + 0j, dtype=np.complex128)).cuda(), v=vt,
+                             tol=1e-8, precision=prec, real_field=rf)
+        assert res["status"] == 0 and res["storage"] == storage, res
+        phi = out.cpu().numpy()
+        if storage == 2:
+            assert np.all(phi.imag == 0.0)
+            _compare(p, phi.real, ref.x, 1e-8, 1e-10, 1e-6)
+        else:
+            _compare(p, phi, ref.x, 1e-8, 1e-10, 1e-6)
+
+
 def test_stop_rule_crit1_sine_1d(dev):
     # §4.1: Algorithm 1 on the sine discretization, crit1 with eps0 = 1e-12,
     # reproduces the printed values; the oracle runs the same rule
