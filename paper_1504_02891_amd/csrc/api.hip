@@ -896,8 +896,10 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       // enough tiles to be bandwidth bound (four workgroups per compute unit)
       // and the tiles are two wavefronts or more (measured: 128^3 with
       // 128-thread tiles 68 -> 49 us per launch; a batch of 64-thread tiles
-      // 129 -> 146 us)
-      const int reread = ((int64_t)g.bm[dim - 1].size() >= kRereadTiles && g.thr[dim - 1] >= 128) ? 1 : 0;
+      // 129 -> 146 us), at 8 points per thread only: with 4 the inputs held
+      // through the transforms fit the registers of two waves per SIMD
+      const int reread = ((int64_t)g.bm[dim - 1].size() >= kRereadTiles && g.thr[dim - 1] >= 128 &&
+                          g.ept[dim - 1] == kE) ? 1 : 0;
       launch_solver_pass(c->s, last, g.prec64, (int)g.bm[dim - 1].size(), g.thr[dim - 1], g.smem[dim - 1], P,
                          s_new, s_new, bmap(g, dim - 1), c->twd, c->twf, par, e0, e1, reread, 0, g.ept[dim - 1],
                          g.pair);
