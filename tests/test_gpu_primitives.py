@@ -3,8 +3,10 @@ retraction, prolongation) against the oracle, through the C ABI.
 
 Tolerance of a spectral pass (rounding analysis of a radix-2^k FFT pair):
 |err| <= C * eps * log2(N) * (max|multiplier| + max|V| + beta max|phi|^2) * max|phi|,
-with eps the unit roundoff of the transform precision and C = 16 (FP64) or
-C = 32 (FP32); reductions accumulate in FP64.
+with eps the unit roundoff of the transform precision and C = 4 in both
+precisions; reductions accumulate in FP64.  Measured on MI355X the worst
+error is about 0.024 of this bound in both precisions (H(phi)phi; the FP32
+Hessian-vector product about 0.016): each test prints its ratio.
 """
 import math
 
@@ -21,7 +23,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 EPS = {"fp64": 2.0 ** -53, "mixed": 2.0 ** -24}
-CFAC = {"fp64": 16.0, "mixed": 32.0}
+CFAC = {"fp64": 4.0, "mixed": 4.0}
 
 
 @pytest.fixture(scope="module")
