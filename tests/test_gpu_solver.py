@@ -166,28 +166,39 @@ def test_cascadic_two_levels(dev):
         _compare_polished(dev, pf, o.cpu().numpy(), x_or, 1e-8, 1e-9)
 
 
+@pytest.mark.parametrize("real", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_cascade_equals_its_levels_composed(dev, prec):
+def test_cascade_equals_its_levels_composed(dev, prec, real):
     # Algorithm 3 as one solve, problems moving between levels on their own,
     # gives each problem the bits of its level-by-level composition: solve to
     # level_tol, prolong, solve the next level, ..., the finest to tol; the
-    # evaluation counters add up over the levels
-    probs = [W.Problem(dim=2, n=(16, 16), lo=(-8.0, -8.0), hi=(8.0, 8.0), beta=b, omega=w)
-             for b, w in ((200.0, 0.2), (400.0, 0.6), (100.0, 0.4))]
-    phis = [W.rotating_initial(p, p.omega, 30 + i) for i, p in enumerate(probs)]
+    # evaluation counters add up over the levels.  Real problems (Omega = 0,
+    # real data) run every level in the real pair storage.
+    if real:
+        probs = [W.Problem(dim=2, n=(16, 16), lo=(-8.0, -8.0), hi=(8.0, 8.0), beta=b, lattice_amp=a)
+                 for b, a in ((200.0, 5.0), (400.0, 0.0), (100.0, 10.0))]
+        phis = [W.gaussian_times_noise(p, 0.02, 30 + i) + 0j for i, p in enumerate(probs)]
+    else:
+        probs = [W.Problem(dim=2, n=(16, 16), lo=(-8.0, -8.0), hi=(8.0, 8.0), beta=b, omega=w)
+                 for b, w in ((200.0, 0.2), (400.0, 0.6), (100.0, 0.4))]
+        phis = [W.rotating_initial(p, p.omega, 30 + i) for i, p in enumerate(probs)]
     levels, ltol, tol = 3, 1e-4, 1e-8
     outs, res = dev.solve_cascadic(probs, [torch.from_numpy(f).cuda() for f in phis], levels,
                                    level_tol=ltol, tol=tol, precision=prec)
     for i, (p, f) in enumerate(zip(probs, phis)):
         cur, pc, nfe, nfe64, inner = torch.from_numpy(f).cuda(), p, 0, 0, 0
         for lv in range(levels):
-            out, r = dev.solve(pc, cur, tol=ltol if lv < levels - 1 else tol, precision=prec)
+            # (a prolonged real function carries rounding noise in its imaginary
+            # part; the cascade keeps a problem's real storage across levels)
+            out, r = dev.solve(pc, cur, tol=ltol if lv < levels - 1 else tol, precision=prec,
+                               real_field=1 if real else -1)
             assert r["status"] == 0, (i, lv, r)
             nfe, nfe64, inner = nfe + r["nfe"], nfe64 + r["nfe_fp64"], inner + r["inner_iters"]
             if lv < levels - 1:
                 pf = pc.with_n(tuple(2 * n for n in pc.n[:pc.dim]))
                 cur, pc = dev.prolong(pc, pf, out), pf
         assert res[i]["status"] == 0, (i, res[i])
+        assert res[i]["storage"] == (2 if real else 0), res[i]
         assert (res[i]["nfe"], res[i]["nfe_fp64"], res[i]["inner_iters"]) == (nfe, nfe64, inner), i
         assert np.array_equal(out.cpu().numpy(), outs[i].cpu().numpy()), i
 
