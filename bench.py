@@ -127,7 +127,7 @@ def cpu_baseline(probs, phi0s, gpu_nfe, budget_s, opts):
     dt1, nfe1 = _oracle_sample((p, phi0, opts["tol"], n_eval))
     spe1 = dt1 / max(nfe1, 1)
     ncpu = os.cpu_count() or 1
-    # one GPU's job gets a share of 16 host cores on the GPU machine
+    # at most 16 worker processes (the host share a one-GPU job is given)
     cores = max(1, min(ncpu, 16))
     t = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
