@@ -905,11 +905,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
                          g.pair);
     }
     if (nodes) record(pev[2 * k + 1]);
-    if (step_at == STEP_KERNEL) {
-      if (count == 1)   // (the descriptor the device holds now: rebuilt maps recapture the chunk)
-        launch_step(c->s, 1, P, S, cur[0].part1, cur[0].partF, cur[0].tiles[0], cur[0].tiles[dim - 1]);
-      else launch_step(c->s, count, P, S);
-    }
+    if (step_at == STEP_KERNEL) launch_step(c->s, count, P, S);
   };
   auto free_events = [&]() {
     for (auto& e : pev)

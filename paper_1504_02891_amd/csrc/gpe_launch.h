@@ -21,12 +21,7 @@ void launch_solver_pass(hipStream_t s, int role, int prec64, int nblocks, int th
 void launch_apply_pass(hipStream_t s, int role, int fp64, int nblocks, int threads, size_t smem,
                        const ProbDev* probs, const ApplyArgs& a, const void* tw);
 // the scalar step of every problem (its precision from its descriptor)
-// the scalar step in its own launch, one workgroup per problem; for a single
-// problem the host may pass its partial-sum arrays and tile counts (part1:
-// first pass, partF: last pass) so that they are read without waiting for
-// the descriptor
-void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, const double* part1 = nullptr,
-                 const double* partF = nullptr, int n1 = 0, int nF = 0);
+void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st);
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64);
 void launch_write_phi(hipStream_t s, const ProbDev* probs, const SolverState* st, int pi, int64_t m, void* phi,
                       int prec64);

@@ -9,14 +9,9 @@ namespace gpe {
 // sums are reduced by the workgroup's wavefronts, slot by slot; the state is
 // copied in with one batch of loads, advanced in registers by one thread and
 // written back whole.
-// DIRECT (a single problem): the partial sums' addresses and counts come as
-// arguments, so their loads go out with the descriptor's and the state's
-// instead of after the descriptor has arrived.
 constexpr int kStepThreads = 512;
-template <bool DIRECT>
 __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict__ probs,
-                                                       SolverState* __restrict__ states, const double* part1,
-                                                       const double* partF, int n1, int nF) {
+                                                       SolverState* __restrict__ states) {
   __shared__ double red[S1_COUNT + SF_COUNT];
   ProbDev P = probs[blockIdx.x];
   pin_reg(P.part1); pin_reg(P.partF); pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
@@ -25,8 +20,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict
   // that their loads go out with the state's
   if (threadIdx.x < 64) touch_lines(states + blockIdx.x);
   double r1[S1_COUNT], rf[SF_COUNT];
-  if constexpr (DIRECT) step_reductions(part1, n1, partF, nF, r1, rf, red);
-  else step_reductions(P.part1, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red);
+  step_reductions(P.part1, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red);
   if (states[blockIdx.x].mode == M_IDLE) return;
   if (threadIdx.x == 0) {
     SolverState L = states[blockIdx.x];
@@ -346,12 +340,8 @@ __global__ void __launch_bounds__(256) k_prolong_fft(const cx<double>* __restric
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st, const double* part1,
-                 const double* partF, int n1, int nF) {
-  if (part1 && nprob == 1)
-    hipLaunchKernelGGL(k_step<true>, dim3(1), dim3(kStepThreads), 0, s, probs, st, part1, partF, n1, nF);
-  else
-    hipLaunchKernelGGL(k_step<false>, dim3(nprob), dim3(kStepThreads), 0, s, probs, st, nullptr, nullptr, 0, 0);
+void launch_step(hipStream_t s, int nprob, const ProbDev* probs, SolverState* st) {
+  hipLaunchKernelGGL(k_step, dim3(nprob), dim3(kStepThreads), 0, s, probs, st);
 }
 void launch_init(hipStream_t s, const ProbDev* probs, int pi, int64_t m, const void* phi0, int prec64) {
   const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
