@@ -316,6 +316,52 @@ __device__ __forceinline__ double wave_reduce_slot(const double* part, int count
   wave_reduce_partials<1>(part + (int64_t)slot * count, count, is_max ? 1u : 0u, a);
   return a[0];
 }
+// Every wavefront reduces all first-pass (S1) slots of `part1` (n1 tiles)
+// and final-pass (SF) slots of `partF` (nF tiles) on its own, with every
+// load of every slot in one batch (B per lane) when the tiles allow it; each
+// slot is summed in the order of wave_reduce_partials (lane l takes tiles l,
+// l + 64, ... in turn), so the bits are those of the step kernel's.
+template <int B>
+__device__ __forceinline__ void wave_reduce_all_b(const double* part1, int n1, const double* partF, int nF,
+                                                  double* r1, double* rf) {
+  const int l = threadIdx.x & 63;
+  double v1[B][S1_COUNT], vf[B][SF_COUNT];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int64_t i1 = min(l + 64 * j, n1 - 1), iF = min(l + 64 * j, nF - 1);
+#pragma unroll
+    for (int s = 0; s < S1_COUNT; ++s) v1[j][s] = gld<double>(part1, (int64_t)s * n1 + i1);
+#pragma unroll
+    for (int s = 0; s < SF_COUNT; ++s) vf[j][s] = gld<double>(partF, (int64_t)s * nF + iF);
+  }
+#pragma unroll
+  for (int s = 0; s < S1_COUNT; ++s) r1[s] = 0.0;
+#pragma unroll
+  for (int s = 0; s < SF_COUNT; ++s) rf[s] = 0.0;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    if (l + 64 * j < n1)
+#pragma unroll
+      for (int s = 0; s < S1_COUNT; ++s) r1[s] = s == S1_RMAX ? fmax(r1[s], v1[j][s]) : r1[s] + v1[j][s];
+    if (l + 64 * j < nF)
+#pragma unroll
+      for (int s = 0; s < SF_COUNT; ++s) rf[s] = s == SF_SMAX ? fmax(rf[s], vf[j][s]) : rf[s] + vf[j][s];
+  }
+  wave_reduce_k<S1_COUNT>(r1, 1u << S1_RMAX);
+  wave_reduce_k<SF_COUNT>(rf, 1u << SF_SMAX);
+}
+__device__ __forceinline__ void wave_reduce_all(const double* part1, int n1, const double* partF, int nF,
+                                                double* r1, double* rf) {
+  const int n = max(n1, nF);
+  if (n <= 64) wave_reduce_all_b<1>(part1, n1, partF, nF, r1, rf);
+  else if (n <= 128) wave_reduce_all_b<2>(part1, n1, partF, nF, r1, rf);
+  else if (n <= 256) wave_reduce_all_b<4>(part1, n1, partF, nF, r1, rf);
+  else {
+    wave_reduce_partials<S1_COUNT>(part1, n1, 1u << S1_RMAX, r1);
+    wave_reduce_partials<SF_COUNT>(partF, nF, 1u << SF_SMAX, rf);
+  }
+}
+
 // The scalar step's reductions spread over the calling workgroup's
 // wavefronts: wavefront w reduces slots w, w + nw, ... of the first-pass (S1)
 // and final-pass (SF) partials, each slot in the fixed order of the
@@ -346,8 +392,7 @@ __device__ __forceinline__ void step_reductions(const double* part1, int n1, con
       for (int s = 0; s < SF_COUNT; ++s) rf[s] = red[S1_COUNT + s];
     }
   } else if (threadIdx.x < 64) {
-    wave_reduce_partials<S1_COUNT>(part1, n1, 1u << S1_RMAX, r1);
-    wave_reduce_partials<SF_COUNT>(partF, nF, 1u << SF_SMAX, rf);
+    wave_reduce_all(part1, n1, partF, nF, r1, rf);   // both slot sets in one batch of loads
   }
 }
 // Fixed-order reduction for a whole workgroup: the first wavefront reduces,
@@ -719,52 +764,6 @@ __device__ __forceinline__ void step_if_last(const ProbDev& P, SolverState* Sg, 
     SolverState L = *Sg;
     step_logic(P, L, r1, rf, prec64);
     *Sg = L;
-  }
-}
-
-// Every wavefront reduces all first-pass (S1) slots of `part1` (n1 tiles)
-// and final-pass (SF) slots of `partF` (nF tiles) on its own, with every
-// load of every slot in one batch (B per lane) when the tiles allow it; each
-// slot is summed in the order of wave_reduce_partials (lane l takes tiles l,
-// l + 64, ... in turn), so the bits are those of the step kernel's.
-template <int B>
-__device__ __forceinline__ void wave_reduce_all_b(const double* part1, int n1, const double* partF, int nF,
-                                                  double* r1, double* rf) {
-  const int l = threadIdx.x & 63;
-  double v1[B][S1_COUNT], vf[B][SF_COUNT];
-#pragma unroll
-  for (int j = 0; j < B; ++j) {
-    const int64_t i1 = min(l + 64 * j, n1 - 1), iF = min(l + 64 * j, nF - 1);
-#pragma unroll
-    for (int s = 0; s < S1_COUNT; ++s) v1[j][s] = gld<double>(part1, (int64_t)s * n1 + i1);
-#pragma unroll
-    for (int s = 0; s < SF_COUNT; ++s) vf[j][s] = gld<double>(partF, (int64_t)s * nF + iF);
-  }
-#pragma unroll
-  for (int s = 0; s < S1_COUNT; ++s) r1[s] = 0.0;
-#pragma unroll
-  for (int s = 0; s < SF_COUNT; ++s) rf[s] = 0.0;
-#pragma unroll
-  for (int j = 0; j < B; ++j) {
-    if (l + 64 * j < n1)
-#pragma unroll
-      for (int s = 0; s < S1_COUNT; ++s) r1[s] = s == S1_RMAX ? fmax(r1[s], v1[j][s]) : r1[s] + v1[j][s];
-    if (l + 64 * j < nF)
-#pragma unroll
-      for (int s = 0; s < SF_COUNT; ++s) rf[s] = s == SF_SMAX ? fmax(rf[s], vf[j][s]) : rf[s] + vf[j][s];
-  }
-  wave_reduce_k<S1_COUNT>(r1, 1u << S1_RMAX);
-  wave_reduce_k<SF_COUNT>(rf, 1u << SF_SMAX);
-}
-__device__ __forceinline__ void wave_reduce_all(const double* part1, int n1, const double* partF, int nF,
-                                                double* r1, double* rf) {
-  const int n = max(n1, nF);
-  if (n <= 64) wave_reduce_all_b<1>(part1, n1, partF, nF, r1, rf);
-  else if (n <= 128) wave_reduce_all_b<2>(part1, n1, partF, nF, r1, rf);
-  else if (n <= 256) wave_reduce_all_b<4>(part1, n1, partF, nF, r1, rf);
-  else {
-    wave_reduce_partials<S1_COUNT>(part1, n1, 1u << S1_RMAX, r1);
-    wave_reduce_partials<SF_COUNT>(partF, nF, 1u << SF_SMAX, rf);
   }
 }
 
