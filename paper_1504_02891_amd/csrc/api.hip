@@ -971,8 +971,36 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   };
   double pass_ms = 0.0;
   int64_t pass_n = 0;
-  void* pin;
-  CHK(pinned_get(c, sizeof(SolverState) * count, &pin));
+  // host checks: each chunk's states are copied to one of two pinned slots
+  // and an event marks the copy.  Without profiling the next chunk is
+  // launched before the host reads the states of the one before, so the
+  // GPU does not wait for the host: a problem that finished (or handed
+  // over, or ended a coarse level) in chunk k only idles through chunk k + 1,
+  // and the host's uploads for it follow chunk k + 1 in stream order.  The
+  // pinned buffer is sized once for the two slots and every upload a check
+  // can make (descriptors, states, block maps), so it never moves meanwhile.
+  const bool pipe = o.profile == 0;
+  const size_t st_bytes = (sizeof(SolverState) * count + 255) / 256 * 256;
+  size_t bm_bytes = 0;
+  for (int gi = 0; gi < ng; ++gi)
+    for (int ax = 0; ax < dim; ++ax) {
+      size_t cap_t = 0;
+      for (int i = 0; i < count; ++i) cap_t += (size_t)grp[gi].pd[i].tiles[ax];
+      bm_bytes += (cap_t * sizeof(int2) + 255) / 256 * 256;
+    }
+  const size_t stage_at = 2 * st_bytes;   // uploads of a check start here
+  const size_t pin_bytes = stage_at + (size_t)count * ((sizeof(ProbDev) + 255) / 256 * 256 +
+                                                       2 * ((sizeof(SolverState) + 255) / 256 * 256)) + bm_bytes;
+  void* pinbase;
+  CHK(pinned_get(c, pin_bytes, &pinbase));
+  hipEvent_t chk_ev[2] = {nullptr, nullptr}, up_ev = nullptr;
+  for (auto& e : chk_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&up_ev, hipEventDisableTiming));
+  bool up_pending = false;   // a check's uploads may still read the staging area (up_ev marks their end)
+  // a problem restarted at a check (hand-over, next level) has its old state
+  // in the next check's copy, taken after the chunk launched ahead: skip it
+  std::vector<char> stale(count, 0);
+  auto slot_ptr = [&](int k) { return (SolverState*)((char*)c->pinned + (size_t)k * st_bytes); };
   const int64_t cap = eval_cap(o) * ng;
   int64_t evals = 0;
   int rc = GPE_OK;
@@ -981,26 +1009,37 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
   const char* prog_env = std::getenv("GPE_PROGRESS");
   const double prog_every = prog_env ? std::atof(prog_env) : 0.0;
   auto prog_last = std::chrono::steady_clock::now();
-  HIPCHK(hipEventRecord(c->t0, c->s));
-  for (;;) {
+  // one chunk of evaluations and the copy of its states to slot k
+  auto launch_chunk = [&](int k) -> bool {
     if (exec) {
-      if (hipGraphLaunch(exec, c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
+      if (hipGraphLaunch(exec, c->s) != hipSuccess) return false;
     } else {
-      for (int k = 0; k < chunk; ++k) enqueue_eval(k);
-      if (enq_err != hipSuccess) { rc = GPE_EDEVICE; break; }
+      for (int e = 0; e < chunk; ++e) enqueue_eval(e);
+      if (enq_err != hipSuccess) return false;
     }
     evals += chunk;
-    if (hipMemcpyAsync(pin, dstate, sizeof(SolverState) * count, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
-        hipStreamSynchronize(c->s) != hipSuccess) {
-      rc = GPE_EDEVICE;
-      break;
-    }
-    // a copy: the uploads below may move the staging buffer
-    const std::vector<SolverState> hs((const SolverState*)pin, (const SolverState*)pin + count);
+    return hipMemcpyAsync(slot_ptr(k), dstate, sizeof(SolverState) * count, hipMemcpyDeviceToHost, c->s) ==
+               hipSuccess &&
+           hipEventRecord(chk_ev[k], c->s) == hipSuccess;
+  };
+  HIPCHK(hipEventRecord(c->t0, c->s));
+  int slot = 0;
+  if (!launch_chunk(slot)) rc = GPE_EDEVICE;
+  std::vector<SolverState> hs;
+  for (; rc == GPE_OK;) {
+    if (pipe && !launch_chunk(slot ^ 1)) { rc = GPE_EDEVICE; break; }
+    if (hipEventSynchronize(chk_ev[slot]) != hipSuccess) { rc = GPE_EDEVICE; break; }
+    const int64_t evals_done = pipe ? evals - chunk : evals;   // evaluations up to the chunk read here
+    hs.assign(slot_ptr(slot), slot_ptr(slot) + count);
     bool all = true;
     int64_t maxnfe = 0;
     std::vector<int> hand, adv;
     for (int i = 0; i < count; ++i) {
+      if (stale[i]) {
+        stale[i] = 0;
+        all = false;
+        continue;
+      }
       maxnfe = std::max<int64_t>(maxnfe, hs[i].nfe);
       if (!done_host[i] && hs[i].done) {
         if (hs[i].status == kStatusStalled && mixed && grp[gof[i]].prec64 == 0) hand.push_back(i);
@@ -1011,9 +1050,9 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     }
     if (o.profile) {
       // launches of this chunk during which some problem was still active
-      const int64_t act = std::min<int64_t>(chunk, std::max<int64_t>(0, maxnfe - (evals - chunk)));
+      const int64_t act = std::min<int64_t>(chunk, std::max<int64_t>(0, maxnfe - (evals_done - chunk)));
       for (int64_t k = 0; k < act; ++k) {
-        if (!sampled(evals - chunk + k)) continue;
+        if (!sampled(evals_done - chunk + k)) continue;
         float e = 0.0f;
         if (hipEventElapsedTime(&e, pev[2 * k], pev[2 * k + 1]) == hipSuccess) {
           pass_ms += e;
@@ -1026,18 +1065,24 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       if (std::chrono::duration<double>(now - prog_last).count() >= prog_every) {
         int fin = 0;
         for (int i = 0; i < count; ++i) fin += done_host[i] ? 1 : 0;
-        std::fprintf(stderr, "gpe: %lld evaluations, %d of %d problems finished\n", (long long)evals, fin, count);
+        std::fprintf(stderr, "gpe: %lld evaluations, %d of %d problems finished\n", (long long)evals_done, fin, count);
         std::fflush(stderr);
         prog_last = now;
       }
     }
     if (all) break;
-    if (evals > cap) { rc = GPE_NOT_CONVERGED; break; }
-    size_t so2 = (sizeof(SolverState) * count + 255) / 256 * 256;   // staging past the state read-back
+    if (evals_done > cap) { rc = GPE_NOT_CONVERGED; break; }
+    size_t so2 = stage_at;   // staging past the two state slots
+    if (up_pending && (!hand.empty() || !adv.empty() || count > 1)) {
+      // the previous check's uploads have left the staging area
+      if (hipEventSynchronize(up_ev) != hipSuccess) { rc = GPE_EDEVICE; break; }
+      up_pending = false;
+    }
     // a problem's new run: its descriptor in group `to`, a fresh state on
     // both state arrays, and its initial data `phi0` (complex128)
     auto restart = [&](int i, int to, const SolverState& s2, const void* phi0) -> int {
       gof[i] = to;
+      stale[i] = pipe ? 1 : 0;
       cur[i] = grp[to].pd[i];
       CHK(upload(c, (ProbDev*)dprob + i, &cur[i], sizeof(ProbDev), so2));
       so2 += (sizeof(ProbDev) + 255) / 256 * 256;
@@ -1086,21 +1131,39 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       rebuild = count > 1 && act * 4 <= grp[gi].bm[dim - 1].size() * 3;
     }
     if (rebuild) {
+      // (the chunk launched ahead may still run from the graph being
+      // replaced: let it finish first)
+      if (pipe && hipStreamSynchronize(c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
       const int r = remap(so2);
       if (r != GPE_OK) { rc = r; break; }
     }
-    if (pinned_get(c, sizeof(SolverState) * count, &pin) != GPE_OK) { rc = GPE_ENOMEM; break; }   // may have grown
+    if (rebuild) {   // (every hand-over or level change rebuilds the maps too)
+      if (hipEventRecord(up_ev, c->s) != hipSuccess) { rc = GPE_EDEVICE; break; }
+      up_pending = true;
+    }
+    if (pipe) slot ^= 1;
+    else if (!launch_chunk(slot)) { rc = GPE_EDEVICE; break; }
   }
+  // the chunk launched ahead has finished before the graph goes
+  const hipError_t fin_err = hipStreamSynchronize(c->s);
+  if (fin_err != hipSuccess && rc >= 0) rc = GPE_EDEVICE;
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   free_events();
+  for (auto& e : chk_ev)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(up_ev);
   if (rc == GPE_EDEVICE) {
     g_last_error = std::string("solver loop: ") + hipGetErrorString(hipGetLastError());
     return rc;
   }
   if (rc < 0) return rc;
   HIPCHK(hipEventRecord(c->t1, c->s));
-  std::memcpy(st.data(), pin, sizeof(SolverState) * count);
+  // the final states (a chunk launched ahead of the last check may have
+  // stepped a problem the evaluation cap stopped)
+  HIPCHK(hipMemcpyAsync(slot_ptr(0), dstate, sizeof(SolverState) * count, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  std::memcpy(st.data(), slot_ptr(0), sizeof(SolverState) * count);
   for (int i = 0; i < count; ++i) {
     launch_write_phi(c->s, P, S, i, grp[gof[i]].pd[i].m, phis[i], grp[gof[i]].prec64);
     // a problem stopped on a coarse level (the solve's evaluation cap, an
