@@ -1095,6 +1095,7 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
     // hand-overs: the FP32 iterate goes to the problem's phi buffer, comes
     // back as the initial point of an FP64 run of the same level with the
     // delta it reached and the rest of its budget
+    int step_err = GPE_OK;   // an error of this check's uploads or launches ends the loop below
     for (int i : hand) {
       deposit(i, hs[i], true);
       bank[i].sw += std::max(1, hs[i].inner_total);
@@ -1107,22 +1108,26 @@ int solve_impl(gpe_ctx* c, int count, const gpe_problem* probs, const gpe_option
       SolverState s2;
       init_state(s2, o2);
       if (o.algorithm != GPE_ALG1) s2.delta = std::min(std::max(hs[i].delta, o.delta_min), o.delta_max);
-      CHK(restart(i, gid(lev[i], 1, pairv[i]), s2, phis[i]));
+      step_err = restart(i, gid(lev[i], 1, pairv[i]), s2, phis[i]);
+      if (step_err != GPE_OK) break;
     }
     // cascade (Algorithm 3): a finished coarse level's iterate goes to the
     // phi buffer, is prolonged to the next grid and starts that level's
     // solve in the options' precision with a fresh state
     for (int i : adv) {
+      if (step_err != GPE_OK) break;
       deposit(i, hs[i], grp[gof[i]].prec64 == 0);
       if (hs[i].status == GPE_NOT_CONVERGED) bank[i].capped = true;
       launch_write_phi(c->s, P, S, i, grp[gof[i]].pd[i].m, phis[i], grp[gof[i]].prec64);
-      CHK(enqueue_prolong(c, pdl[lev[i]][i], phis[i], level_buf(i)));
+      step_err = enqueue_prolong(c, pdl[lev[i]][i], phis[i], level_buf(i));
+      if (step_err != GPE_OK) break;
       ++lev[i];
       SolverState s2;
       init_state(s2, level_opts(lev[i]));
-      CHK(restart(i, gid(lev[i], 0, pairv[i]), s2, level_buf(i)));
+      step_err = restart(i, gid(lev[i], 0, pairv[i]), s2, level_buf(i));
     }
-    HIPCHK(hipGetLastError());
+    if (step_err == GPE_OK && hipGetLastError() != hipSuccess) step_err = GPE_EDEVICE;
+    if (step_err != GPE_OK) { rc = step_err; break; }
     bool rebuild = !hand.empty() || !adv.empty();
     for (int gi = 0; gi < ng && !rebuild; ++gi) {
       size_t act = 0;
