@@ -227,6 +227,28 @@ def test_error_paths(dev):
     assert res["status"] == 1 and np.isfinite(res["energy"])
 
 
+def test_cascade_error_paths(dev):
+    # a level past 1024 points per axis, a sine problem, and a problem whose
+    # data are not finite: its coarse level ends in error and the cascade
+    # still hands back a finest-grid array (its coarse iterate prolonged)
+    from paper_1504_02891_amd.api import GpeError
+    p = W.Problem(dim=2, n=(512, 512), lo=(-8.0, -8.0), hi=(8.0, 8.0), beta=100.0, omega=0.2)
+    f = torch.from_numpy(W.rotating_initial(p, 0.2, 3)).cuda()
+    with pytest.raises(GpeError) as e:
+        dev.solve_cascadic([p], [f], 3)          # 512 -> 1024 -> 2048
+    assert e.value.status == -2
+    q = W.Problem(dim=2, n=(32, 32), lo=(-8.0, -8.0), hi=(8.0, 8.0), bc=W.SINE, beta=100.0)
+    with pytest.raises(GpeError) as e:
+        dev.solve_cascadic([q], [torch.ones((31, 31), dtype=torch.complex128, device="cuda")], 2)
+    assert e.value.status == -2
+    r = W.Problem(dim=2, n=(32, 32), lo=(-8.0, -8.0), hi=(8.0, 8.0), beta=100.0, omega=0.3)
+    g = W.rotating_initial(r, 0.3, 4)
+    g[5, 7] = np.nan
+    with pytest.raises(GpeError) as e:
+        dev.solve_cascadic([r], [torch.from_numpy(g).cuda()], 3)
+    assert e.value.status == -5
+
+
 @pytest.mark.parametrize("case", ["rot2d-mixed", "lattice3d-fp64", "lattice3d-128-mixed-capped"])
 def test_step_placements_agree(dev, case):
     # where the scalar step runs (own launch, last workgroup of the final
