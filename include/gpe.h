@@ -294,10 +294,15 @@ int gpe_solve(gpe_ctx* ctx, const gpe_problem* prob, const gpe_options* opts,
 
 /*
  * `count` independent problems solved together: every evaluation step runs
- * all unfinished problems in the same kernel launches.  Problems may differ
- * in beta, Omega, V and n (same dim).  phis[i]: DEVICE complex128 arrays.
- * results: HOST array of `count`.  Returns GPE_OK if every problem
- * converged, GPE_NOT_CONVERGED if any did not, or the first error.
+ * all unfinished problems in the same kernel launches (one launch per pass
+ * for each group of problems that share a precision and a storage; in mixed
+ * precision a problem moves to the FP64 group when it hands over, at the
+ * host check after it does, while the others go on).  Problems may differ
+ * in beta, Omega, V, discretization and n (same dim); each problem's
+ * trajectory is that of the same problem solved alone.  phis[i]: DEVICE
+ * complex128 arrays.  results: HOST array of `count`.  Returns GPE_OK if
+ * every problem converged, GPE_NOT_CONVERGED if any did not, or the first
+ * error.
  */
 int gpe_solve_batched(gpe_ctx* ctx, int32_t count, const gpe_problem* probs,
                       const gpe_options* opts, void* const* phis, gpe_result* results);
