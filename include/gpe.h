@@ -299,7 +299,8 @@ int gpe_solve(gpe_ctx* ctx, const gpe_problem* prob, const gpe_options* opts,
  * precision a problem moves to the FP64 group when it hands over, at the
  * host check after it does, while the others go on).  Problems may differ
  * in beta, Omega, V, discretization and n (same dim); each problem's
- * trajectory is that of the same problem solved alone.  phis[i]: DEVICE
+ * trajectory is that of the same problem solved alone with the same launch
+ * plan.  phis[i]: DEVICE
  * complex128 arrays.  results: HOST array of `count`.  Returns GPE_OK if
  * every problem converged, GPE_NOT_CONVERGED if any did not, or the first
  * error.
