@@ -315,6 +315,33 @@ def batch_leg(api, torch, np, opts):
     return out
 
 
+def lattice_leg(api, torch, np, a, opts):
+    """The 3D lattice (128^3, real data: the solver's real storage), the
+    bandwidth-heavy single-grid workload: timed solves in each precision and
+    the final pass's roofline from one profiled mixed solve."""
+    probs, phi0s, desc = workload("lattice3d")
+    phis = [torch.from_numpy(np.asarray(f, dtype=np.complex128)).cuda() for f in phi0s]
+    install_plans(api, probs, ("mixed", "fp64"), 1, False)
+    out = {"workload": desc}
+    for prec, reps in (("mixed", 3), ("fp64", 2)):
+        o = dict(opts, precision=prec)
+        api.solve(probs[0], phis[0], **o)                  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, r = api.solve(probs[0], phis[0], **o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"value": round(reps / dt, 4), "unit": "solves/s", "converged": r["status"] == 0,
+                     "nfe": r["nfe"], "fp32_evaluations": int(sum(r["nfe_mixed"])), "storage": r["storage"],
+                     "energy": r["energy"], "resid": r["resid"]}
+    if a.profile_every > 0:
+        la = argparse.Namespace(workload="lattice3d", profile_every=a.profile_every)
+        _, r = api.solve(probs[0], phis[0], **dict(opts, precision="mixed", profile=a.profile_every, use_graph=0))
+        out["roofline"] = roofline(la, probs, [[r]], False)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -464,6 +491,7 @@ def main():
                        "energy": [r["energy"] for r in r64[-1]][:4], "resid": [r["resid"] for r in r64[-1]][:4]}
     if a.workload == "rot2d" and not a.no_batch:
         out["batch2d"] = batch_leg(api, torch, np, dict(tol=a.tol, max_outer=a.max_outer))
+        out["lattice3d"] = lattice_leg(api, torch, np, a, dict(tol=a.tol, max_outer=a.max_outer))
     if not a.no_hphi:
         out["hphi"] = hphi_bandwidth(HPHI_BIG)
         out["hphi_256"] = hphi_bandwidth()
