@@ -227,6 +227,23 @@ def test_error_paths(dev):
     assert res["status"] == 1 and np.isfinite(res["energy"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_and_plain_launches_agree(dev, prec):
+    # the host loop launches each chunk ahead of the check of the one before,
+    # as a replayed hipGraph or as plain launches (profiling forces plain
+    # launches and checks in turn): the same evaluations, the same bits
+    p = W.Problem(dim=2, n=(64, 64), lo=(-10.0, -10.0), hi=(10.0, 10.0), beta=500.0, omega=0.25)
+    phi0 = W.rotating_initial(p, 0.25, 2)
+    outs = []
+    for kw in (dict(use_graph=1), dict(use_graph=0), dict(use_graph=0, profile=7)):
+        phi, res = _gpu_solve(dev, p, phi0, tol=1e-8, precision=prec, **kw)
+        assert res["status"] == 0, (kw, res)
+        outs.append((phi, res["nfe"], res["energy"]))
+    for phi, nfe, e in outs[1:]:
+        assert nfe == outs[0][1] and e == outs[0][2]
+        assert np.array_equal(phi, outs[0][0])
+
+
 def test_cascade_error_paths(dev):
     # a level past 1024 points per axis, a sine problem, and a problem whose
     # data are not finite: its coarse level ends in error and the cascade
