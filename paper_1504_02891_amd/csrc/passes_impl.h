@@ -316,6 +316,28 @@ __device__ __forceinline__ double wave_reduce_slot(const double* part, int count
   wave_reduce_partials<1>(part + (int64_t)slot * count, count, is_max ? 1u : 0u, a);
   return a[0];
 }
+// One slot's partials (count <= 64 B) loaded into registers by a wavefront,
+// then summed in the order of wave_reduce_partials (the same bits).
+constexpr int kNyLoads = 4;
+template <int B>
+struct SlotLoads {
+  double v[B];
+  __device__ __forceinline__ void load(const double* part, int count) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[j] = gld<double>(part, min(l + 64 * j, count - 1));
+  }
+  __device__ __forceinline__ double sum(int count) const {
+    const int l = threadIdx.x & 63;
+    double a[1] = {0.0};
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (l + 64 * j < count) a[0] += v[j];
+    wave_reduce_k<1>(a, 0u);
+    return a[0];
+  }
+};
+
 // Every wavefront reduces all first-pass (S1) slots of `part1` (n1 tiles)
 // and final-pass (SF) slots of `partF` (nF tiles) on its own, with every
 // load of every slot in one batch (B per lane) when the tiles allow it; each
@@ -647,19 +669,31 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   cx<CT> tv[E];
   typename Tile<N, E, PAIR>::VP vp[E];
   constexpr bool LATE = EPI && RR;
+  // loads in the order of use: the trial point's inputs first, so that the
+  // transforms wait for those alone (loads return in order), then what only
+  // the end of the pass needs (t, V, the first pass's norm partials)
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    in[e] = ops.load(T.g(e));
-    if constexpr (HAS_T && !LATE) tv[e] = ld<CT>(P.t, T.g(e));
-  }
+  for (int e = 0; e < E; ++e) in[e] = ops.load(T.g(e));
+  if constexpr (HAS_T && !LATE)
+#pragma unroll
+    for (int e = 0; e < E; ++e) tv[e] = ld<CT>(P.t, T.g(e));
   if constexpr (EPI && !LATE) T.pot_load(P, vp);
   double c = 1.0, n_hat = 1.0;
-  if constexpr (ROLE == R_FINAL) {
-    // every wavefront reduces the first pass's norm partials itself
-    const double ny = wave_reduce_slot(P.part1, P.tiles[0], S1_NY, false);
+  // every wavefront of the final pass reduces the first pass's norm partials
+  // itself; with 4 points per thread, no re-read epilogue and at most 256
+  // first-pass tiles their loads go out here and the sum is taken after the
+  // transforms (elsewhere the registers are needed more)
+  constexpr bool EARLY_NY = ROLE == R_FINAL && !LATE && E == 4;
+  const bool early_ny = EARLY_NY && P.tiles[0] <= 64 * kNyLoads;
+  SlotLoads<kNyLoads> nyl;
+  if constexpr (EARLY_NY)
+    if (early_ny) nyl.load(P.part1 + (int64_t)S1_NY * P.tiles[0], P.tiles[0]);
+  auto renorm = [&](double ny) {
     c = renorm_c(S, ny);
     n_hat = c * c * ny;
-  }
+  };
+  if constexpr (ROLE == R_FINAL)
+    if (!early_ny) renorm(wave_reduce_slot(P.part1, P.tiles[0], S1_NY, false));
   twf.store(lds);
   cx<CT> v[E];
   Acc1 a1;
@@ -687,6 +721,8 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
   if constexpr (PAIR && ROLE == R_FIRST) pair_to_line<N, E, CT>(T, v, lds + N);
   spectral_apply<N, E, CT>(P, ax, T, v, lds);
   if constexpr (PAIR && ROLE == R_FIRST) line_to_pair<N, E, CT>(T, v, lds + N);
+  if constexpr (EARLY_NY)
+    if (early_ny) renorm(nyl.sum(P.tiles[0]));
   if constexpr (ROLE == R_FIRST) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
