@@ -396,6 +396,42 @@ __device__ __forceinline__ void wave_reduce_k(double* acc, unsigned maxmask) {
   for (int i = 0; i < K; ++i) acc[i] = lane63(acc[i]);
 }
 
+// K values per lane reduced over one wavefront through LDS (a transpose),
+// with the bits of wave_reduce_k: its butterfly is the balanced pairwise tree
+// over the lanes in order (pairs, quads, eights, rows, then rows 2-3 and 0-1),
+// and every step commutes.  The values are written slot-major, a row of 65
+// doubles per slot; lane 4k + q (k < K) sums lanes 16q .. 16q + 15 of slot k
+// as that tree, then the quad combines its four row sums (partner xor 1, then
+// xor 2).  Lanes 4k .. 4k + 3 return slot k (a max where bit k of `maxmask`
+// is set, of non-negative values), the other lanes 0.  `buf` holds K * 65
+// doubles of LDS that only the calling wavefront touches.
+template <int K>
+__device__ __forceinline__ double wave_reduce_lds(const double* acc, unsigned maxmask, double* buf) {
+  static_assert(4 * K <= 64, "one quad of lanes per slot");
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < K; ++i) buf[i * 65 + l] = acc[i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int k = l >> 2, q = l & 3;
+  const bool mx = k < K && ((maxmask >> k) & 1u);
+  const double* p = buf + min(k, K - 1) * 65 + 16 * q;
+  double v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = p[m];
+#pragma unroll
+  for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+    for (int m = 0; m < w; ++m) v[m] = mx ? fmax(v[2 * m], v[2 * m + 1]) : v[2 * m] + v[2 * m + 1];
+  double s = v[0];
+  double u = dpp_d<0xb1, 0xf>(s);   // quad_perm [1,0,3,2]
+  s = mx ? fmax(s, u) : s + u;
+  u = dpp_d<0x4e, 0xf>(s);          // quad_perm [2,3,0,1]
+  s = mx ? fmax(s, u) : s + u;
+  return k < K ? s : 0.0;
+}
+
 // Partial sums are stored slot-major, part[s * count + i] for slot s of
 // workgroup (tile) i, so that reading one slot of consecutive tiles is
 // coalesced.

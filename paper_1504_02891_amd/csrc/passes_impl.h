@@ -728,12 +728,19 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
     for (int e = 0; e < E; ++e)
       if (T.inner(e)) stc<CT>(P.t, T.g(e), v[e]);
     double acc[3] = {a1.ny, a1.np2, a1.rmax};
-    block_reduce<2, 1>(acc, red);
-    if (threadIdx.x == 0) {
-      const int64_t nt = P.tiles[0];
-      gst<double>(P.part1, S1_NY * nt + tile, acc[0]);
-      gst<double>(P.part1, S1_NP2 * nt + tile, acc[1]);
-      gst<double>(P.part1, S1_RMAX * nt + tile, acc[2]);
+    const int64_t nt = P.tiles[0];
+    if (blockDim.x == 64) {
+      // one wavefront: slot k's sum lands in lane 4k, which stores it
+      const double r = wave_reduce_lds<S1_COUNT>(acc, 1u << S1_RMAX, red);
+      if ((threadIdx.x & 3) == 0 && (threadIdx.x >> 2) < S1_COUNT)
+        gst<double>(P.part1, (threadIdx.x >> 2) * nt + tile, r);
+    } else {
+      block_reduce<2, 1>(acc, red);
+      if (threadIdx.x == 0) {
+        gst<double>(P.part1, S1_NY * nt + tile, acc[0]);
+        gst<double>(P.part1, S1_NP2 * nt + tile, acc[1]);
+        gst<double>(P.part1, S1_RMAX * nt + tile, acc[2]);
+      }
     }
   } else if constexpr (ROLE == R_MID) {
 #pragma unroll
@@ -765,11 +772,16 @@ __device__ __forceinline__ void solver_tile(const ProbDev& P, const SolverState&
 #pragma unroll
     for (int i = 0; i < SF_COUNT_SUM; ++i) acc[i] = af.s[i];
     acc[SF_SMAX] = af.smax;
-    block_reduce<SF_COUNT_SUM, 1>(acc, red);
-    if (threadIdx.x == 0) {
-      const int64_t nt = pick3(P.tiles, P.dim - 1);
+    const int64_t nt = pick3(P.tiles, P.dim - 1);
+    if (blockDim.x == 64) {
+      const double r = wave_reduce_lds<SF_COUNT>(acc, 1u << SF_SMAX, red);
+      if ((threadIdx.x & 3) == 0 && (threadIdx.x >> 2) < SF_COUNT)
+        gst<double>(P.partF, (threadIdx.x >> 2) * nt + tile, r);
+    } else {
+      block_reduce<SF_COUNT_SUM, 1>(acc, red);
+      if (threadIdx.x == 0)
 #pragma unroll
-      for (int i = 0; i < SF_COUNT; ++i) gst<double>(P.partF, i * nt + tile, acc[i]);
+        for (int i = 0; i < SF_COUNT; ++i) gst<double>(P.partF, i * nt + tile, acc[i]);
     }
   }
 }
@@ -883,7 +895,8 @@ __global__ void __launch_bounds__(256) k_solver_pass(const ProbDev* __restrict__
                                                      const cx<double>* __restrict__ twd,
                                                      const cx<float>* __restrict__ twf, int par) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[SF_COUNT * 16];
+  // the block reduction's scratch, or the one-wavefront transpose's
+  __shared__ double red[SF_COUNT * 65 > SF_COUNT * 16 ? SF_COUNT * 65 : SF_COUNT * 16];
   const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int2 bm = bmap ? bmap[b] : make_int2(0, b);
   // local copies, read in one batch: the fields the pass needs pinned in
