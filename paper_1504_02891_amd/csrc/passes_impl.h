@@ -372,6 +372,42 @@ __device__ __forceinline__ void wave_reduce_all_b(const double* part1, int n1, c
   wave_reduce_k<S1_COUNT>(r1, 1u << S1_RMAX);
   wave_reduce_k<SF_COUNT>(rf, 1u << SF_SMAX);
 }
+// wave_reduce_all_b's per-lane sums (the same loads and order), combined over
+// the lanes by wave_reduce_lds, one lane quad per slot (the same bits); lane
+// 4k writes slot k (first-pass slots, then final-pass slots) to out[k].
+// `tbuf` holds (S1_COUNT + SF_COUNT) * 65 doubles of LDS.
+template <int B>
+__device__ __forceinline__ void wave_reduce_all_lds(const double* part1, int n1, const double* partF, int nF,
+                                                    double* tbuf, double* out) {
+  constexpr int NS = S1_COUNT + SF_COUNT;
+  static_assert(4 * NS <= 64, "one lane quad per slot");
+  const int l = threadIdx.x & 63;
+  double v1[B][S1_COUNT], vf[B][SF_COUNT];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int64_t i1 = min(l + 64 * j, n1 - 1), iF = min(l + 64 * j, nF - 1);
+#pragma unroll
+    for (int s = 0; s < S1_COUNT; ++s) v1[j][s] = gld<double>(part1, (int64_t)s * n1 + i1);
+#pragma unroll
+    for (int s = 0; s < SF_COUNT; ++s) vf[j][s] = gld<double>(partF, (int64_t)s * nF + iF);
+  }
+  double acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    if (l + 64 * j < n1)
+#pragma unroll
+      for (int s = 0; s < S1_COUNT; ++s) acc[s] = s == S1_RMAX ? fmax(acc[s], v1[j][s]) : acc[s] + v1[j][s];
+    if (l + 64 * j < nF)
+#pragma unroll
+      for (int s = 0; s < SF_COUNT; ++s)
+        acc[S1_COUNT + s] = s == SF_SMAX ? fmax(acc[S1_COUNT + s], vf[j][s]) : acc[S1_COUNT + s] + vf[j][s];
+  }
+  const double r = wave_reduce_lds<NS>(acc, (1u << S1_RMAX) | (1u << (S1_COUNT + SF_SMAX)), tbuf);
+  if ((l & 3) == 0) out[l >> 2] = r;
+}
+
 __device__ __forceinline__ void wave_reduce_all(const double* part1, int n1, const double* partF, int nF,
                                                 double* r1, double* rf) {
   const int n = max(n1, nF);
@@ -388,10 +424,12 @@ __device__ __forceinline__ void wave_reduce_all(const double* part1, int n1, con
 // wavefronts: wavefront w reduces slots w, w + nw, ... of the first-pass (S1)
 // and final-pass (SF) partials, each slot in the fixed order of the
 // one-wavefront reduction (the same bits), and thread 0 gets r1 and rf
-// through `red` (at least S1_COUNT + SF_COUNT doubles).  Every thread of the
-// workgroup must call it (barrier).
+// through `red` (at least S1_COUNT + SF_COUNT doubles).  With `tbuf`
+// ((S1_COUNT + SF_COUNT) * 65 doubles of LDS) and at most 256 tiles the one
+// wavefront combines its lanes through LDS (the same bits).  Every thread of
+// the workgroup must call it (barrier).
 __device__ __forceinline__ void step_reductions(const double* part1, int n1, const double* partF, int nF,
-                                                double* r1, double* rf, double* red) {
+                                                double* r1, double* rf, double* red, double* tbuf = nullptr) {
   constexpr int NS = S1_COUNT + SF_COUNT, BS = 32;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
   // rounds of dependent loads: one wavefront with every slot's loads in
@@ -412,6 +450,21 @@ __device__ __forceinline__ void step_reductions(const double* part1, int n1, con
       for (int s = 0; s < S1_COUNT; ++s) r1[s] = red[s];
 #pragma unroll
       for (int s = 0; s < SF_COUNT; ++s) rf[s] = red[S1_COUNT + s];
+    }
+  } else if (tbuf != nullptr && cnt <= 256) {
+    if (threadIdx.x < 64) {
+      if (cnt <= 64) wave_reduce_all_lds<1>(part1, n1, partF, nF, tbuf, red);
+      else if (cnt <= 128) wave_reduce_all_lds<2>(part1, n1, partF, nF, tbuf, red);
+      else wave_reduce_all_lds<4>(part1, n1, partF, nF, tbuf, red);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < S1_COUNT; ++s) r1[s] = red[s];
+#pragma unroll
+        for (int s = 0; s < SF_COUNT; ++s) rf[s] = red[S1_COUNT + s];
+      }
     }
   } else if (threadIdx.x < 64) {
     wave_reduce_all(part1, n1, partF, nF, r1, rf);   // both slot sets in one batch of loads
