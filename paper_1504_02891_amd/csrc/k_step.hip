@@ -5,32 +5,26 @@
 
 namespace gpe {
 
-// Scalar step as its own launch (one workgroup per problem): the first
-// wavefront reduces the partial sums (all wavefronts, slot by slot, when there
-// are many tiles) while the second stages the state in LDS, so that the two
-// reads overlap; one thread advances the state in registers and writes it
-// back whole.
+// Scalar step as its own launch (one workgroup per problem): the partial
+// sums are reduced by the first wavefront (all wavefronts, slot by slot, when
+// there are many tiles); the state is copied in with one batch of loads,
+// advanced in registers by one thread and written back whole.
 constexpr int kStepThreads = 512;
-constexpr int kStateWords = (int)(sizeof(SolverState) / 16);
-static_assert(kStateWords <= kStepThreads - 64, "the second wavefront onward stages the state");
 __global__ void __launch_bounds__(kStepThreads) k_step(const ProbDev* __restrict__ probs,
                                                        SolverState* __restrict__ states) {
   __shared__ double red[S1_COUNT + SF_COUNT];
   __shared__ double tbuf[(S1_COUNT + SF_COUNT) * 65];
-  __shared__ SolverState sl;
-  if (threadIdx.x >= 64 && threadIdx.x < 64 + kStateWords) {
-    const int w = threadIdx.x - 64;
-    reinterpret_cast<uint4*>(&sl)[w] = gld<uint4>(states + blockIdx.x, w);
-  }
   ProbDev P = probs[blockIdx.x];
   pin_reg(P.part1); pin_reg(P.partF); pin_reg(P.tiles[0]); pin_reg(P.tiles[1]); pin_reg(P.tiles[2]);
   pin_reg(P.dim); pin_reg(P.sqrt_hvol); pin_reg(P.prec64);
+  // the partial sums are reduced before the state is known to need them, so
+  // that their loads go out with the state's
+  if (threadIdx.x < 64) touch_lines(states + blockIdx.x);
   double r1[S1_COUNT], rf[SF_COUNT];
   step_reductions(P.part1, P.tiles[0], P.partF, pick3(P.tiles, P.dim - 1), r1, rf, red, tbuf);
-  __syncthreads();
-  if (sl.mode == M_IDLE) return;
+  if (states[blockIdx.x].mode == M_IDLE) return;
   if (threadIdx.x == 0) {
-    SolverState L = sl;
+    SolverState L = states[blockIdx.x];
     step_logic(P, L, r1, rf, P.prec64);
     states[blockIdx.x] = L;
   }
